@@ -1,0 +1,147 @@
+/* dmrg.h -- C ABI of the spin-adapted two-site DMRG hot path on MI355X (gfx950).
+ *
+ * The operation is the Davidson matrix-vector product of the two-site DMRG
+ * step, H_eff psi = V^T H V psi, for the ab-initio Hamiltonian of the paper's
+ * Sec. "Complete active space SCF" (integrals h_pq and (pq|rs), read with the
+ * standard pairing and the factor 1/2 on the two-electron term) restricted to
+ * the variational space of a spin-adapted matrix product state (Sec. "Tensor
+ * network states and density matrix renormalization group"; bond dimension D
+ * counts SU(2) multiplets as in Sec. "Conservation of the total spin").  The
+ * loop around it -- Davidson with residual norm 1e-7 (Sec. "Numerical
+ * procedure"), truncation to D multiplets and the renormalisation of the
+ * operator blocks -- is exposed as well.
+ *
+ * Conventions
+ *   - Every call returns int: 0 = DMRG_OK, < 0 = error; dmrg_last_error()
+ *     gives a thread-local message.  Arguments are validated on the host
+ *     before any GPU work is queued.
+ *   - Host arrays are C row-major FP64, owned by the caller, copied before
+ *     return and never retained.  *_dev pointers are device pointers borrowed
+ *     for the duration of the call.
+ *   - Orbitals are 0-based in chain order.  h is n*n, g is n^4 with
+ *     g[p][q][r][s] = (pq|rs) (chemists' notation, 8-fold symmetric).
+ *   - Local multiplets per site: sigma = 0 (empty), 1 (doublet), 2 (doubly
+ *     occupied).  Creation-operator order is orbital-major, up before down.
+ *   - The two-site block is (k, k+1).  Bonds 0..k carry the (N, 2S) of the
+ *     block of sites to their left, bonds k+2..n the (N, 2S) of the block of
+ *     sites to their right; bond k+1 is inside the two-site block and is
+ *     passed with zero sectors.  Bonds 0 and n hold the single sector (0,0,1).
+ *   - Site tensors: sites j < k are left-canonical, blocks (l, sigma, a) of
+ *     shape D_l x D_a with N_a = N_l + N_sigma and triangle(S_l, s_sigma, S_a),
+ *     coupling the block state l and the site (in that order) to a.  Sites
+ *     j >= k+2 are right-canonical, blocks (c, sigma, r) of shape D_c x D_r with
+ *     N_c = N_sigma + N_r, coupling the site and the block state r (in that
+ *     order) to c.  Blocks are ordered by (first sector, sigma, second sector),
+ *     sector indices in bond order; each block is row-major.  The concatenation
+ *     over sites 0..k-1 then k+2..n-1 is the `blocks` argument.
+ *   - psi is coupled as ((l sigma1) S_a, (sigma2 r) S_c) S and stored as dense
+ *     super-blocks (a, c) with N_a + N_c = N and triangle(S_a, S_c, S), sorted by
+ *     (N_a, 2S_a, 2S_c); rows are the (l, sigma1) sub-blocks sorted by
+ *     (l, sigma1), columns the (sigma2, r) sub-blocks sorted by (sigma2, r).
+ */
+#ifndef DMRG_MI355X_H
+#define DMRG_MI355X_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DMRG_OK = 0,
+  DMRG_ERR_ARG = -1,       /* null pointer, bad enum, k out of range           */
+  DMRG_ERR_SHAPE = -2,     /* inconsistent sizes, wrong block counts            */
+  DMRG_ERR_SYMMETRY = -3,  /* N and 2S parity mismatch, impossible sector       */
+  DMRG_ERR_BUDGET = -4,    /* device allocation failed / over hbm budget        */
+  DMRG_ERR_HIP = -5,       /* HIP runtime error                                  */
+  DMRG_ERR_NOCONV = -6,    /* Davidson not converged; outputs hold best iterate */
+  DMRG_ERR_NONFINITE = -7  /* NaN or Inf in an input                             */
+};
+
+typedef enum { DMRG_FP64 = 0, DMRG_FP32 = 1, DMRG_BF16 = 2 } dmrg_prec;
+
+typedef struct dmrg_ctx dmrg_ctx;
+
+typedef struct {
+  int n_orb;                   /* active orbitals n                                  */
+  int n_elec;                  /* active electrons N                                 */
+  int two_s;                   /* twice the total spin                               */
+  double e_core;               /* constant added to every energy                     */
+  double davidson_tol;         /* residual 2-norm threshold (paper: 1e-7)            */
+  int davidson_max_iter;       /* outer iterations per davidson_step                 */
+  int davidson_max_subspace;   /* basis size before restart                          */
+  int hpsi_prec;               /* dmrg_prec used for the bulk matvecs in Davidson    */
+  long long work_budget_elems; /* cap on intermediate buffers (elements), 0: default */
+} dmrg_opts;
+
+/* Create a context; copies h (n*n) and g (n^4).  Errors: ARG, SYMMETRY
+ * (N odd with 2S even, N > 2n, ...), NONFINITE. */
+int dmrg_create(dmrg_ctx **out, const dmrg_opts *opts, const double *h, const double *g);
+
+/* Load a mixed-canonical MPS around the two-site block (k, k+1) and build the
+ * left operator block at bond k and the right operator block at bond k+2 on
+ * the GPU.  bond_sectors: sum(sectors_per_bond) rows of (N, 2S, dim) int32;
+ * sectors_per_bond: n+1 counts.  Errors: ARG, SHAPE, SYMMETRY, NONFINITE,
+ * BUDGET, HIP. */
+int dmrg_set_mps(dmrg_ctx *c, int k, const int *bond_sectors, const int *sectors_per_bond,
+                 const double *blocks, long long n_values);
+
+/* psi layout at the current two-site block: number of super-blocks, total
+ * length, and (if desc != NULL) 7 values per super-block:
+ * (N_a, 2S_a, N_c, 2S_c, rows, cols, offset). */
+int dmrg_psi_layout(dmrg_ctx *c, int k, long long *n_superblocks, long long *desc, long long *n_elems);
+
+/* psi_out = H_eff psi_in at block (k, k+1) (host buffers of n_elems FP64).
+ * prec selects the arithmetic of the contraction (FP64 exact path, FP32 or
+ * BF16 operands with FP32 accumulation).  flops_out (nullable) receives the
+ * algorithmic flop count (sum of 2mnk over structurally non-zero block
+ * products, identities excluded). */
+int dmrg_hpsi(dmrg_ctx *c, int k, const double *psi_in, double *psi_out, int prec, double *flops_out);
+
+/* Same on device buffers (FP64, n_elems each), on the library's stream. */
+int dmrg_hpsi_dev(dmrg_ctx *c, int k, const void *d_in, void *d_out, int prec);
+
+/* Diagonal of H_eff at the current block (host, n_elems). */
+int dmrg_heff_diag(dmrg_ctx *c, int k, double *diag);
+
+/* Davidson for the lowest eigenpair of H_eff at block (k, k+1), starting from
+ * psi_inout (host, n_elems; a zero vector selects a random start).  Bulk
+ * matvecs in opts.hpsi_prec, residuals and Rayleigh-Ritz in FP64 with FP64
+ * correction matvecs.  On return psi_inout holds the normalised eigenvector,
+ * energy the eigenvalue plus e_core, resid_norm ||H x - E x||_2.
+ * Returns NOCONV (outputs still written) if tol is not reached. */
+int dmrg_davidson_step(dmrg_ctx *c, int k, double *psi_inout, double *energy, double *resid_norm,
+                       int *n_matvec_lowprec, int *n_matvec_fp64);
+
+/* Truncate psi at the middle cut to at most d_max multiplets (eps_tr > 0
+ * additionally drops the smallest weights while their sum stays below eps_tr),
+ * absorb the left part into a new left-canonical tensor A at site k, and grow
+ * the left operator block to bond k+1 (direction +1).  trunc_err receives the
+ * discarded weight, d_kept the kept multiplet count.  The singular values of
+ * the cut (kept ones, descending per sector) can be read with dmrg_cut_spectrum. */
+int dmrg_truncate(dmrg_ctx *c, int k, const double *psi, int direction, int d_max, double eps_tr,
+                  double *trunc_err, int *d_kept);
+
+/* Reduced singular values of the last truncation (all sectors, descending),
+ * with their sector spins 2S; returns the count in *n. */
+int dmrg_cut_spectrum(dmrg_ctx *c, double *values, int *two_s, int *n, int capacity);
+
+/* Counters: out[0] = flops of one H*psi, out[1] = bytes of operator blocks
+ * (left + right, FP64), out[2] = peak device bytes, out[3] = number of terms,
+ * out[4] = number of block-product tasks per H*psi. */
+int dmrg_stats(dmrg_ctx *c, double *out, int n);
+
+/* Kernel self-test: C (m x n) = beta*C + alpha * op(A) op(B) through the same
+ * grouped MFMA kernel the hot path uses (host FP64 buffers; A is m x k or,
+ * with trans_a, k x m row-major; B is k x n or n x k).  ident_a / ident_b
+ * replace the operand by the identity (k must then equal m / n).  prec as in
+ * dmrg_hpsi: operands are rounded to it, accumulation is FP64 (FP64) or FP32. */
+int dmrg_gemm_selftest(int m, int n, int k, const double *A, int trans_a, int ident_a, const double *B,
+                       int trans_b, int ident_b, double alpha, double beta, double *C, int prec);
+
+const char *dmrg_last_error(void);
+void dmrg_destroy(dmrg_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

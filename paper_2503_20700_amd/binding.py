@@ -1,0 +1,200 @@
+"""ctypes binding of the C ABI declared in include/dmrg.h (argument marshalling only).
+
+Every computation happens in the native library; this module converts numpy
+arrays to pointers, checks return codes and raises ``DMRGError`` with the
+library's message.  The library is loaded from the package's ``_lib``
+directory (built by ``__graft_entry__.build()``); if it is missing the import
+of this module succeeds but constructing ``DMRG`` raises immediately -- there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_LIB = os.path.join(_HERE, "_lib", "libdmrg_mi355x.so")
+
+FP64, FP32, BF16 = 0, 1, 2
+ERRORS = {-1: "ARG", -2: "SHAPE", -3: "SYMMETRY", -4: "BUDGET", -5: "HIP", -6: "NOCONV", -7: "NONFINITE"}
+
+
+class DMRGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ct.Structure):
+    _fields_ = [("n_orb", ct.c_int), ("n_elec", ct.c_int), ("two_s", ct.c_int), ("e_core", ct.c_double),
+                ("davidson_tol", ct.c_double), ("davidson_max_iter", ct.c_int),
+                ("davidson_max_subspace", ct.c_int), ("hpsi_prec", ct.c_int),
+                ("work_budget_elems", ct.c_longlong)]
+
+
+_LIBS = {}
+
+
+def load(path=None):
+    path = os.path.abspath(path or os.environ.get("DMRG_MI355X_LIB", DEFAULT_LIB))
+    if path in _LIBS:
+        return _LIBS[path]
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"native library not built: {path} (run __graft_entry__.build())")
+    lib = ct.CDLL(path)
+    P, I, D, LL, V = ct.c_void_p, ct.c_int, ct.c_double, ct.c_longlong, None
+    dp = ct.POINTER(ct.c_double)
+    ip = ct.POINTER(ct.c_int)
+    llp = ct.POINTER(ct.c_longlong)
+    sig = {
+        "dmrg_create": (I, [ct.POINTER(P), ct.POINTER(Opts), dp, dp]),
+        "dmrg_set_mps": (I, [P, I, ip, ip, dp, LL]),
+        "dmrg_psi_layout": (I, [P, I, llp, llp, llp]),
+        "dmrg_hpsi": (I, [P, I, dp, dp, I, dp]),
+        "dmrg_hpsi_dev": (I, [P, I, P, P, I]),
+        "dmrg_heff_diag": (I, [P, I, dp]),
+        "dmrg_davidson_step": (I, [P, I, dp, dp, dp, ip, ip]),
+        "dmrg_truncate": (I, [P, I, dp, I, I, D, dp, ip]),
+        "dmrg_cut_spectrum": (I, [P, dp, ip, ip, I]),
+        "dmrg_stats": (I, [P, dp, I]),
+        "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
+        "dmrg_last_error": (ct.c_char_p, []),
+        "dmrg_destroy": (V, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIBS[path] = lib
+    return lib
+
+
+def exported_symbols():
+    return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_heff_diag",
+            "dmrg_davidson_step", "dmrg_truncate", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
+            "dmrg_last_error", "dmrg_destroy"]
+
+
+def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ident_b=False, alpha=1.0, beta=0.0,
+                  prec=FP64, lib=None):
+    """C = beta*C + alpha op(A) op(B) through the library's grouped MFMA kernel."""
+    lib = load(lib)
+    if ident_a:
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        k, n = (B.shape[1], B.shape[0]) if trans_b else B.shape
+        m = k
+    else:
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        m, k = (A.shape[1], A.shape[0]) if trans_a else A.shape
+        if ident_b:
+            n = k
+        else:
+            B = np.ascontiguousarray(B, dtype=np.float64)
+            n = B.shape[0] if trans_b else B.shape[1]
+    C = np.zeros((m, n)) if C is None else np.ascontiguousarray(C, dtype=np.float64).copy()
+    dummy = np.zeros(1)
+    rc = lib.dmrg_gemm_selftest(m, n, k, _dp(dummy if ident_a else A), int(trans_a), int(ident_a),
+                                _dp(dummy if ident_b else B), int(trans_b), int(ident_b), alpha, beta, _dp(C), prec)
+    if rc != 0:
+        raise DMRGError(rc, lib.dmrg_last_error().decode())
+    return C
+
+
+def _dp(a):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+class DMRG:
+    """One context: integrals, an MPS around a two-site block, and its H*psi."""
+
+    def __init__(self, h, g, n_elec, two_s, e_core=0.0, davidson_tol=1e-7, davidson_max_iter=60,
+                 davidson_max_subspace=16, hpsi_prec=FP64, work_budget_elems=0, lib=None):
+        self.lib = load(lib)
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        n = h.shape[0]
+        self.opts = Opts(n, n_elec, two_s, e_core, davidson_tol, davidson_max_iter, davidson_max_subspace,
+                         hpsi_prec, work_budget_elems)
+        self._h = ct.c_void_p()
+        self._check(self.lib.dmrg_create(ct.byref(self._h), ct.byref(self.opts), _dp(h), _dp(g)))
+        self.k = None
+
+    def _check(self, rc):
+        if rc != 0:
+            raise DMRGError(rc, self.lib.dmrg_last_error().decode())
+        return rc
+
+    def close(self):
+        if self._h:
+            self.lib.dmrg_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_mps(self, k, bond_sectors, sectors_per_bond, blocks):
+        bs = np.ascontiguousarray(bond_sectors, dtype=np.int32).reshape(-1)
+        cnt = np.ascontiguousarray(sectors_per_bond, dtype=np.int32)
+        blk = np.ascontiguousarray(blocks, dtype=np.float64)
+        self._check(self.lib.dmrg_set_mps(self._h, k, bs.ctypes.data_as(ct.POINTER(ct.c_int)),
+                                          cnt.ctypes.data_as(ct.POINTER(ct.c_int)), _dp(blk), blk.size))
+        self.k = k
+
+    def psi_layout(self):
+        nsb, nel = ct.c_longlong(), ct.c_longlong()
+        self._check(self.lib.dmrg_psi_layout(self._h, self.k, ct.byref(nsb), None, ct.byref(nel)))
+        desc = np.zeros(7 * nsb.value, dtype=np.int64)
+        self._check(self.lib.dmrg_psi_layout(self._h, self.k, ct.byref(nsb),
+                                             desc.ctypes.data_as(ct.POINTER(ct.c_longlong)), ct.byref(nel)))
+        return desc.reshape(-1, 7), nel.value
+
+    def hpsi(self, psi, prec=FP64):
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        out = np.empty_like(psi)
+        fl = ct.c_double()
+        self._check(self.lib.dmrg_hpsi(self._h, self.k, _dp(psi), _dp(out), prec, ct.byref(fl)))
+        return out, fl.value
+
+    def hpsi_dev(self, d_in, d_out, prec=FP64):
+        self._check(self.lib.dmrg_hpsi_dev(self._h, self.k, ct.c_void_p(d_in), ct.c_void_p(d_out), prec))
+
+    def heff_diag(self, size):
+        out = np.empty(size)
+        self._check(self.lib.dmrg_heff_diag(self._h, self.k, _dp(out)))
+        return out
+
+    def davidson(self, psi0):
+        psi = np.ascontiguousarray(psi0, dtype=np.float64).copy()
+        e, r = ct.c_double(), ct.c_double()
+        nlo, nhi = ct.c_int(), ct.c_int()
+        rc = self.lib.dmrg_davidson_step(self._h, self.k, _dp(psi), ct.byref(e), ct.byref(r), ct.byref(nlo),
+                                         ct.byref(nhi))
+        if rc not in (0, -6):
+            self._check(rc)
+        return dict(psi=psi, energy=e.value, resid=r.value, n_lo=nlo.value, n_fp64=nhi.value, converged=rc == 0)
+
+    def truncate(self, psi, d_max, eps_tr=0.0, direction=1):
+        psi = np.ascontiguousarray(psi, dtype=np.float64)
+        err, kept = ct.c_double(), ct.c_int()
+        self._check(self.lib.dmrg_truncate(self._h, self.k, _dp(psi), direction, d_max, eps_tr, ct.byref(err),
+                                           ct.byref(kept)))
+        return err.value, kept.value
+
+    def cut_spectrum(self, capacity=1 << 20):
+        vals = np.zeros(capacity)
+        spins = np.zeros(capacity, dtype=np.int32)
+        n = ct.c_int()
+        self._check(self.lib.dmrg_cut_spectrum(self._h, _dp(vals), spins.ctypes.data_as(ct.POINTER(ct.c_int)),
+                                               ct.byref(n), capacity))
+        return vals[:n.value].copy(), spins[:n.value].copy()
+
+    def stats(self):
+        out = np.zeros(5)
+        self._check(self.lib.dmrg_stats(self._h, _dp(out), 5))
+        return dict(hpsi_flops=out[0], op_bytes=out[1], peak_bytes=out[2], n_terms=int(out[3]),
+                    n_tasks=int(out[4]))

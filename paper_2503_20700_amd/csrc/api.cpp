@@ -1,0 +1,280 @@
+// C ABI: argument validation, MPS ingestion, operator-block build and the
+// H*psi driver.  See include/dmrg.h for the contract.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/dmrg.h"
+#include "planner.hpp"
+#include "session.hpp"
+#include "su2.hpp"
+
+using namespace dmrg;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+}  // namespace
+
+extern "C" const char* dmrg_last_error(void) { return g_err.c_str(); }
+
+extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, const double* g) {
+  if (!out || !o || !h || !g) return fail(DMRG_ERR_ARG, "dmrg_create: null argument");
+  *out = nullptr;
+  const int n = o->n_orb;
+  if (n < 2 || n > 256) return fail(DMRG_ERR_ARG, "dmrg_create: n_orb must be in [2, 256]");
+  if (o->n_elec < 0 || o->n_elec > 2 * n) return fail(DMRG_ERR_SYMMETRY, "dmrg_create: N out of range");
+  if (o->two_s < 0 || ((o->n_elec + o->two_s) & 1) || o->two_s > std::min(o->n_elec, 2 * n - o->n_elec))
+    return fail(DMRG_ERR_SYMMETRY, "dmrg_create: 2S incompatible with N");
+  if (o->hpsi_prec < 0 || o->hpsi_prec > 2) return fail(DMRG_ERR_ARG, "dmrg_create: bad hpsi_prec");
+  const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+  if (!finite_all(h, n2) || !finite_all(g, n4)) return fail(DMRG_ERR_NONFINITE, "dmrg_create: non-finite integral");
+  try {
+    auto s = std::make_unique<dmrg_ctx>();
+    s->opts = *o;
+    Integrals I;
+    I.n = n;
+    I.h.assign(h, h + n2);
+    I.g.assign(g, g + n4);
+    I.e_core = o->e_core;
+    s->ex.reset(make_hip_executor());
+    s->C = std::make_unique<Context>(s->ex.get(), I, o->n_elec, o->two_s);
+    *out = s.release();
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_create: ") + e.what());
+  }
+}
+
+extern "C" void dmrg_destroy(dmrg_ctx* c) { delete c; }
+
+extern "C" int dmrg_set_mps(dmrg_ctx* c, int k, const int* bs, const int* counts, const double* blocks,
+                            long long n_values) {
+  if (!c || !bs || !counts || (!blocks && n_values > 0)) return fail(DMRG_ERR_ARG, "dmrg_set_mps: null argument");
+  Context& C = *c->C;
+  const int n = C.n;
+  if (k < 0 || k > n - 2) return fail(DMRG_ERR_ARG, "dmrg_set_mps: k out of range");
+  // ---- bonds
+  std::vector<Bond> bonds(n + 1);
+  size_t pos = 0;
+  for (int b = 0; b <= n; ++b) {
+    if (counts[b] < 0) return fail(DMRG_ERR_SHAPE, "dmrg_set_mps: negative sector count");
+    for (int i = 0; i < counts[b]; ++i, ++pos) {
+      Sector s{bs[3 * pos], bs[3 * pos + 1], bs[3 * pos + 2]};
+      if (s.dim <= 0) return fail(DMRG_ERR_SHAPE, "dmrg_set_mps: non-positive sector dimension");
+      if (s.n < 0 || s.s2 < 0 || ((s.n + s.s2) & 1)) return fail(DMRG_ERR_SYMMETRY, "dmrg_set_mps: sector parity");
+      const int m = (b <= k) ? b : n - b;  // orbitals in the block this bond describes
+      if (s.n > 2 * m || s.s2 > std::min(s.n, 2 * m - s.n))
+        return fail(DMRG_ERR_SYMMETRY, "dmrg_set_mps: sector impossible for its block");
+      if (bonds[b].find(s.n, s.s2) >= 0) return fail(DMRG_ERR_SHAPE, "dmrg_set_mps: duplicate sector");
+      bonds[b].secs.push_back(s);
+    }
+    if (b == k + 1 && counts[b] != 0) return fail(DMRG_ERR_SHAPE, "dmrg_set_mps: bond k+1 must be empty");
+  }
+  auto is_vac = [](const Bond& bd) {
+    return bd.secs.size() == 1 && bd.secs[0].n == 0 && bd.secs[0].s2 == 0 && bd.secs[0].dim == 1;
+  };
+  if (!is_vac(bonds[0]) || !is_vac(bonds[n])) return fail(DMRG_ERR_SHAPE, "dmrg_set_mps: bonds 0 and n must be (0,0,1)");
+  // ---- site tensors
+  std::vector<SiteTensor> sites(n);
+  long long need = 0;
+  for (int j = 0; j < n; ++j) {
+    if (j == k || j == k + 1) continue;
+    SiteTensor& T = sites[j];
+    T.left = j < k;
+    T.j = j;
+    const Bond& b0 = bonds[j];
+    const Bond& b1 = bonds[j + 1];
+    int64_t off = 0;
+    for (size_t i0 = 0; i0 < b0.secs.size(); ++i0)
+      for (int sig = 0; sig < 3; ++sig)
+        for (size_t i1 = 0; i1 < b1.secs.size(); ++i1) {
+          const Sector &s0 = b0.secs[i0], &s1 = b1.secs[i1];
+          bool ok = T.left ? (s1.n == s0.n + kLocN[sig] && tri2(s0.s2, kLocS2[sig], s1.s2))
+                           : (s0.n == kLocN[sig] + s1.n && tri2(kLocS2[sig], s1.s2, s0.s2));
+          if (!ok) continue;
+          T.find[{(int)i0, sig, (int)i1}] = (int)T.blocks.size();
+          T.blocks.push_back(SiteTensor::Blk{(int)i0, sig, (int)i1, off, s0.dim, s1.dim});
+          off += (int64_t)s0.dim * s1.dim;
+        }
+    need += off;
+  }
+  if (need != n_values) return fail(DMRG_ERR_SHAPE, "dmrg_set_mps: number of tensor values does not match the sectors");
+  if (!finite_all(blocks, (size_t)n_values)) return fail(DMRG_ERR_NONFINITE, "dmrg_set_mps: non-finite tensor value");
+  try {
+    c->reset_plan();
+    C.Lblk.reset();
+    C.Rblk.reset();
+    for (auto& T : C.sites) C.free_buf(T.buf);
+    C.k = k;
+    C.bonds = bonds;
+    const double* src = blocks;
+    for (int j = 0; j < n; ++j) {
+      if (j == k || j == k + 1) continue;
+      int64_t sz = 0;
+      for (auto& bl : sites[j].blocks) sz += (int64_t)bl.rows * bl.cols;
+      sites[j].buf = C.new_buf(std::max<int64_t>(sz, 1));
+      if (sz) C.ex->upload(C.ptr(sites[j].buf), src, (size_t)sz * 8);
+      src += sz;
+    }
+    C.sites = std::move(sites);
+    // ---- operator blocks
+    auto L = C.vacuum_left();
+    for (int j = 0; j < k; ++j) {
+      auto N = C.grow_left(*L, C.sites[j], C.bonds[j + 1]);
+      C.free_block(*L);
+      L = std::move(N);
+    }
+    auto R = C.vacuum_right();
+    for (int j = n - 1; j >= k + 2; --j) {
+      auto N = C.grow_right(*R, C.sites[j], C.bonds[j]);
+      C.free_block(*R);
+      R = std::move(N);
+    }
+    C.Lblk = std::move(L);
+    C.Rblk = std::move(R);
+    return DMRG_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(DMRG_ERR_BUDGET, "dmrg_set_mps: out of memory");
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_set_mps: ") + e.what());
+  }
+}
+
+extern "C" int dmrg_psi_layout(dmrg_ctx* c, int k, long long* nsb, long long* desc, long long* nel) {
+  if (!c || !nsb || !nel) return fail(DMRG_ERR_ARG, "dmrg_psi_layout: null argument");
+  if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_psi_layout: no MPS loaded at this k");
+  try {
+    c->ensure_plan();
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_psi_layout: ") + e.what());
+  }
+  const PsiLayout& lay = c->plan->lay;
+  *nsb = (long long)lay.sbs.size();
+  *nel = lay.size;
+  if (desc)
+    for (size_t i = 0; i < lay.sbs.size(); ++i) {
+      const auto& s = lay.sbs[i];
+      long long* d = desc + 7 * i;
+      d[0] = s.an; d[1] = s.as2; d[2] = s.cn; d[3] = s.cs2; d[4] = s.nrows; d[5] = s.ncols; d[6] = s.off;
+    }
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_hpsi(dmrg_ctx* c, int k, const double* in, double* out, int prec, double* flops) {
+  if (!c || !in || !out) return fail(DMRG_ERR_ARG, "dmrg_hpsi: null argument");
+  if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_hpsi: no MPS loaded at this k");
+  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "dmrg_hpsi: bad precision");
+  try {
+    c->ensure_plan();
+    const int64_t n = c->plan->lay.size;
+    if (!finite_all(in, (size_t)n)) return fail(DMRG_ERR_NONFINITE, "dmrg_hpsi: non-finite input");
+    c->C->ex->upload(c->C->ptr(c->b_in), in, (size_t)n * 8);
+    c->hpsi_device(prec);
+    c->C->ex->download(out, c->C->ptr(c->b_out), (size_t)n * 8);
+    if (flops) *flops = c->plan->flops;
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_hpsi: ") + e.what());
+  }
+}
+
+extern "C" int dmrg_hpsi_dev(dmrg_ctx* c, int k, const void* din, void* dout, int prec) {
+  if (!c || !din || !dout) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev: null argument");
+  if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev: no MPS loaded at this k");
+  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev: bad precision");
+  try {
+    c->ensure_plan();
+    const int64_t n = c->plan->lay.size;
+    c->C->ex->copy_d2d(c->C->ptr(c->b_in), din, (size_t)n * 8);
+    c->hpsi_device(prec);
+    c->C->ex->copy_d2d(dout, c->C->ptr(c->b_out), (size_t)n * 8);
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_hpsi_dev: ") + e.what());
+  }
+}
+
+extern "C" int dmrg_heff_diag(dmrg_ctx* c, int k, double* diag) {
+  if (!c || !diag) return fail(DMRG_ERR_ARG, "dmrg_heff_diag: null argument");
+  if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_heff_diag: no MPS loaded at this k");
+  try {
+    c->ensure_plan();
+    c->ex->download(diag, c->C->ptr(c->b_diag), (size_t)c->plan->lay.size * 8);
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_heff_diag: ") + e.what());
+  }
+}
+
+extern "C" int dmrg_gemm_selftest(int m, int n, int k, const double* A, int ta, int ia, const double* B, int tb,
+                                  int ib, double alpha, double beta, double* C, int prec) {
+  if (m <= 0 || n <= 0 || k <= 0 || !C || (!ia && !A) || (!ib && !B)) return fail(DMRG_ERR_ARG, "gemm_selftest: bad args");
+  if ((ia && k != m) || (ib && k != n)) return fail(DMRG_ERR_SHAPE, "gemm_selftest: identity needs k == m / n");
+  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "gemm_selftest: bad precision");
+  try {
+    std::unique_ptr<Executor> ex(make_hip_executor());
+    const int dt = prec == DMRG_FP64 ? DT_F64 : prec == DMRG_FP32 ? DT_F32 : DT_BF16;
+    const int dc = prec == DMRG_FP64 ? DT_F64 : DT_F32;
+    auto put = [&](const double* h, size_t cnt, int d) -> void* {
+      void* p64 = ex->alloc(cnt * 8);
+      ex->upload(p64, h, cnt * 8);
+      if (d == DT_F64) return p64;
+      void* p = ex->alloc(cnt * dtype_size(d));
+      ex->convert(p, d, p64, DT_F64, cnt);
+      ex->sync();
+      ex->release(p64);
+      return p;
+    };
+    void* dA = ia ? nullptr : put(A, (size_t)m * k, dt);
+    void* dB = ib ? nullptr : put(B, (size_t)k * n, dt);
+    std::vector<double> cb((size_t)m * n);
+    for (size_t i = 0; i < cb.size(); ++i) cb[i] = beta * C[i];
+    void* dC = put(cb.data(), cb.size(), dc);
+    RawJob j{dC, m, n, n, 1, 0, 0, 1};
+    RawTerm t{dA, dB, ta ? m : k, tb ? k : n, k, (ta ? TF_TRANS_A : 0) | (tb ? TF_TRANS_B : 0) |
+                                                 (ia ? TF_IDENT_A : 0) | (ib ? TF_IDENT_B : 0), alpha};
+    void* h = ex->prepare({j}, {t}, dt, dt, dc);
+    ex->run(h);
+    ex->sync();
+    ex->drop(h);
+    void* c64 = dC;
+    if (dc != DT_F64) {
+      c64 = ex->alloc(cb.size() * 8);
+      ex->convert(c64, DT_F64, dC, dc, cb.size());
+      ex->sync();
+    }
+    ex->download(C, c64, cb.size() * 8);
+    for (void* p : {dA, dB, dC}) if (p) ex->release(p);
+    if (c64 != dC) ex->release(c64);
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("gemm_selftest: ") + e.what());
+  }
+}
+
+extern "C" int dmrg_stats(dmrg_ctx* c, double* out, int n) {
+  if (!c || !out) return fail(DMRG_ERR_ARG, "dmrg_stats: null argument");
+  double v[5] = {0, 0, 0, 0, 0};
+  if (c->plan) {
+    v[0] = c->plan->flops;
+    v[3] = (double)c->plan->terms.size();
+    v[4] = (double)c->plan->n_stage_terms;
+  }
+  if (c->C->Lblk) v[1] = (double)(c->C->Lblk->bytes_f64() + c->C->Rblk->bytes_f64());
+  v[2] = (double)c->C->peak_bytes;
+  for (int i = 0; i < n && i < 5; ++i) out[i] = v[i];
+  return DMRG_OK;
+}

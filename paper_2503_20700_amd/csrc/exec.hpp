@@ -1,0 +1,94 @@
+// Device-side work description shared by the planner and the HIP executor.
+//
+// All block-sparse contractions on the hot path (renormalisation of the
+// operator blocks, the two stages of H*psi, and linear combinations of
+// operators) are expressed as one primitive: a list of output matrices
+// ("jobs"), each accumulating a list of scaled products
+//     C  (+)=  sum_t alpha_t * op(A_t) @ op(B_t)
+// where op() is identity or transpose and either factor may be the identity
+// matrix.  Every output region is owned by exactly one job, so the executor
+// needs no atomics and sums in a fixed order (bitwise reproducible).
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace dmrg {
+
+enum DType : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_FP8 = 3 };
+inline size_t dtype_size(int dt) { return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : dt == DT_BF16 ? 2 : 1; }
+
+enum TermFlags : int { TF_TRANS_A = 1, TF_TRANS_B = 2, TF_IDENT_A = 4, TF_IDENT_B = 8 };
+
+// Pointers are element offsets into named buffers, resolved per precision.
+struct BufRef {
+  int buf = -1;
+  int64_t off = 0;
+};
+
+struct GemmTerm {
+  BufRef A, B;
+  int64_t lda = 0, ldb = 0;
+  int k = 0, flags = 0;
+  double alpha = 1.0;
+};
+
+struct GemmJob {
+  BufRef C;
+  int m = 0, n = 0;
+  int64_t ldc = 0;
+  int accumulate = 0;
+  int64_t tbeg = 0, tend = 0;
+};
+
+struct GemmBatch {
+  std::vector<GemmJob> jobs;
+  std::vector<GemmTerm> terms;
+  double flops = 0.0;  // algorithmic 2mnk over non-identity products
+  void clear() {
+    jobs.clear();
+    terms.clear();
+    flops = 0.0;
+  }
+};
+
+// Resolved (raw pointer) forms uploaded to the device.
+struct RawTerm {
+  const void* A;
+  const void* B;
+  int64_t lda, ldb;
+  int k, flags;
+  double alpha;
+};
+struct RawJob {
+  void* C;
+  int m, n;
+  int64_t ldc;
+  int accumulate, pad;
+  int64_t tbeg, tend;
+};
+
+class Executor {
+ public:
+  virtual ~Executor() {}
+  virtual void* alloc(size_t bytes) = 0;
+  virtual void release(void* p) = 0;
+  virtual void upload(void* dst, const void* src, size_t bytes) = 0;
+  virtual void download(void* dst, const void* src, size_t bytes) = 0;
+  virtual void zero(void* p, size_t bytes) = 0;
+  virtual void copy_d2d(void* dst, const void* src, size_t bytes) = 0;
+  // Prepare a batch whose A/B operands have dtype tin and whose outputs have
+  // dtype tout (both F64 for the exact path).  Returns an opaque handle.
+  virtual void* prepare(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int tin_a,
+                        int tin_b, int tout) = 0;
+  virtual void run(void* handle) = 0;
+  virtual void drop(void* handle) = 0;
+  virtual void sync() = 0;
+  // element-wise precision conversion of n values
+  virtual void convert(void* dst, int dt_dst, const void* src, int dt_src, size_t n) = 0;
+};
+
+// The product executor (HIP, gfx950).
+Executor* make_hip_executor();
+
+}  // namespace dmrg

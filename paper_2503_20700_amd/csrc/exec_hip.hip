@@ -1,0 +1,343 @@
+// HIP executor for gfx950 (MI355X): grouped, segmented-K block GEMM on MFMA.
+//
+// One launch executes a list of output matrices ("jobs"); each job is split
+// into 64x64 tiles and every tile is owned by one work-group (4 wavefronts of
+// 64 lanes, each wave a 32x32 quadrant = 2x2 MFMA 16x16 blocks).  The tile loops
+// over all products of its job (K concatenated over products), staging 64xK
+// slabs of A and B through LDS, and writes (or accumulates into) C once, so
+// there are no atomics and the summation order is fixed.
+//
+// Arithmetic paths:
+//   F64  : v_mfma_f64_16x16x4f64, operands and accumulation in FP64
+//   F32  : v_mfma_f32_16x16x4f32, FP32 operands, FP32 accumulation
+//   BF16 : v_mfma_f32_16x16x32_bf16, BF16 operands (RNE), FP32 accumulation
+// Operands may be stored in a wider type than the arithmetic (they are
+// rounded while being staged into LDS); outputs are written in their own type.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <type_traits>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "exec.hpp"
+
+namespace dmrg {
+namespace {
+
+#define HIP_OK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) throw std::runtime_error(std::string("HIP: ") + hipGetErrorString(e_) + " at " #x); \
+  } while (0)
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+constexpr int TM = 64, TN = 64;
+
+__device__ __forceinline__ u16 f2bf(float f) {
+  unsigned int b = __float_as_uint(f);
+  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (u16)((b >> 16) | 0x40);  // quiet NaN
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return (u16)(b >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float(((unsigned int)h) << 16); }
+
+template <int DT>
+__device__ __forceinline__ double ldv(const void* p, long long i) {
+  if constexpr (DT == DT_F64) return ((const double*)p)[i];
+  else if constexpr (DT == DT_F32) return (double)((const float*)p)[i];
+  else return (double)bf2f(((const u16*)p)[i]);
+}
+template <int DT>
+__device__ __forceinline__ float ldf(const void* p, long long i) {
+  if constexpr (DT == DT_F64) return (float)((const double*)p)[i];
+  else if constexpr (DT == DT_F32) return ((const float*)p)[i];
+  else return bf2f(((const u16*)p)[i]);
+}
+template <int DT, typename V>
+__device__ __forceinline__ void stv(void* p, long long i, V v) {
+  if constexpr (DT == DT_F64) ((double*)p)[i] = (double)v;
+  else if constexpr (DT == DT_F32) ((float*)p)[i] = (float)v;
+  else ((u16*)p)[i] = f2bf((float)v);
+}
+
+// MODE: DT_F64 / DT_F32 / DT_BF16 arithmetic; DA/DB/DC storage types.
+template <int MODE, int DA, int DB, int DC>
+__global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms,
+                                                   const int* __restrict__ tiles) {
+  using acc_t = typename std::conditional<MODE == DT_F64, d4, f4>::type;
+  using sc_t = typename std::conditional<MODE == DT_F64, double, float>::type;
+  constexpr int KT = (MODE == DT_BF16) ? 32 : 16;
+  // F64/F32: LDS k-major [KT][TM+1]; BF16: row-major [TM][KT+8] of bf16 bits
+  constexpr int LDS_A = (MODE == DT_BF16) ? TM * (KT + 8) * 2 : KT * (TM + 1) * (MODE == DT_F64 ? 8 : 4);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * LDS_A];
+  unsigned char* sA = smem;
+  unsigned char* sB = smem + LDS_A;
+
+  const int tid = threadIdx.x;
+  const int job = tiles[3 * blockIdx.x], ti = tiles[3 * blockIdx.x + 1], tj = tiles[3 * blockIdx.x + 2];
+  const RawJob J = jobs[job];
+  const int m0 = ti * TM, n0 = tj * TN;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  acc_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
+
+  for (long long t = J.tbeg; t < J.tend; ++t) {
+    const RawTerm T = terms[t];
+    const int K = T.k;
+    if (T.flags & (TF_IDENT_A | TF_IDENT_B)) {
+      // C += alpha * (the other operand): read it at this lane's accumulator positions.
+      const bool ia = T.flags & TF_IDENT_A;
+      const void* P = ia ? T.B : T.A;
+      const long long ld = ia ? T.ldb : T.lda;
+      const bool tr = ia ? (T.flags & TF_TRANS_B) : (T.flags & TF_TRANS_A);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = m0 + wm + a * 16 + 4 * lg + v;
+            const int col = n0 + wn + b * 16 + lr;
+            if (row < J.m && col < J.n) {
+              const long long idx = tr ? (long long)col * ld + row : (long long)row * ld + col;
+              const double x = ia ? ldv<DB>(P, idx) : ldv<DA>(P, idx);
+              acc[a][b][v] += (sc_t)(T.alpha * x);
+            }
+          }
+      continue;
+    }
+    const bool ta = T.flags & TF_TRANS_A, tb = T.flags & TF_TRANS_B;
+    const sc_t alpha = (sc_t)T.alpha;
+    for (int k0 = 0; k0 < K; k0 += KT) {
+      // ---- stage A (TM x KT) and B (KT x TN) into LDS
+      constexpr int PER = TM * KT / 256;
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int idx = tid + 256 * r;
+        int i, kk;
+        if (!ta) { i = idx / KT; kk = idx % KT; } else { kk = idx / TM; i = idx % TM; }
+        const int gi = m0 + i, gk = k0 + kk;
+        sc_t v = 0;
+        if (gi < J.m && gk < K) {
+          const long long g = ta ? (long long)gk * T.lda + gi : (long long)gi * T.lda + gk;
+          if constexpr (MODE == DT_F64) v = (sc_t)ldv<DA>(T.A, g) * alpha;
+          else v = ldf<DA>(T.A, g) * alpha;
+        }
+        if constexpr (MODE == DT_BF16) ((u16*)sA)[i * (KT + 8) + kk] = f2bf(v);
+        else ((sc_t*)sA)[kk * (TM + 1) + i] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int idx = tid + 256 * r;
+        int j, kk;
+        if (!tb) { kk = idx / TN; j = idx % TN; } else { j = idx / KT; kk = idx % KT; }
+        const int gj = n0 + j, gk = k0 + kk;
+        sc_t v = 0;
+        if (gj < J.n && gk < K) {
+          const long long g = tb ? (long long)gj * T.ldb + gk : (long long)gk * T.ldb + gj;
+          if constexpr (MODE == DT_F64) v = (sc_t)ldv<DB>(T.B, g);
+          else v = ldf<DB>(T.B, g);
+        }
+        if constexpr (MODE == DT_BF16) ((u16*)sB)[j * (KT + 8) + kk] = f2bf(v);
+        else ((sc_t*)sB)[kk * (TN + 1) + j] = v;
+      }
+      __syncthreads();
+      // ---- MFMA
+      if constexpr (MODE == DT_BF16) {
+        bf8 av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = *(const bf8*)&((const u16*)sA)[(wm + a * 16 + lr) * (KT + 8) + 8 * lg];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = *(const bf8*)&((const u16*)sB)[(wn + b * 16 + lr) * (KT + 8) + 8 * lg];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < KT; kk += 4) {
+          const sc_t* A_ = (const sc_t*)sA;
+          const sc_t* B_ = (const sc_t*)sB;
+          sc_t a0 = A_[(kk + lg) * (TM + 1) + wm + lr];
+          sc_t a1 = A_[(kk + lg) * (TM + 1) + wm + 16 + lr];
+          sc_t b0 = B_[(kk + lg) * (TN + 1) + wn + lr];
+          sc_t b1 = B_[(kk + lg) * (TN + 1) + wn + 16 + lr];
+          if constexpr (MODE == DT_F64) {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+          } else {
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // ---- write back (row = 4*lg + v, col = lr inside each 16x16 block)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + a * 16 + 4 * lg + v;
+        const int col = n0 + wn + b * 16 + lr;
+        if (row < J.m && col < J.n) {
+          const long long o = (long long)row * J.ldc + col;
+          if (J.accumulate) {
+            if constexpr (DC == DT_F64) ((double*)J.C)[o] += (double)acc[a][b][v];
+            else stv<DC>(J.C, o, ldv<DC>(J.C, o) + (double)acc[a][b][v]);
+          } else {
+            stv<DC>(J.C, o, acc[a][b][v]);
+          }
+        }
+      }
+}
+
+template <int DS, int DD>
+__global__ void convert_kernel(void* dst, const void* src, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    stv<DD>(dst, i, ldv<DS>(src, i));
+}
+
+struct Prepared {
+  RawJob* d_jobs = nullptr;
+  RawTerm* d_terms = nullptr;
+  int* d_tiles = nullptr;
+  long long ntiles = 0;
+  int mode = DT_F64, da = DT_F64, db = DT_F64, dc = DT_F64;
+};
+
+using KernelFn = void (*)(const RawJob*, const RawTerm*, const int*);
+
+KernelFn pick(int mode, int da, int db, int dc) {
+#define K_(M, A, B, C) \
+  if (mode == M && da == A && db == B && dc == C) return gemm_kernel<M, A, B, C>;
+  K_(DT_F64, DT_F64, DT_F64, DT_F64)
+  K_(DT_F32, DT_F32, DT_F32, DT_F32)
+  K_(DT_BF16, DT_BF16, DT_BF16, DT_BF16)
+  K_(DT_BF16, DT_BF16, DT_BF16, DT_F32)
+#undef K_
+  throw std::runtime_error("executor: unsupported dtype combination");
+}
+
+class HipExec : public Executor {
+ public:
+  HipExec() { HIP_OK(hipStreamCreate(&stream_)); }
+  ~HipExec() override {
+    if (stream_) hipStreamDestroy(stream_);
+  }
+  void* alloc(size_t bytes) override {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    return p;
+  }
+  void release(void* p) override {
+    if (p) HIP_OK(hipFree(p));
+  }
+  void upload(void* d, const void* s, size_t b) override {
+    if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyHostToDevice, stream_));
+    HIP_OK(hipStreamSynchronize(stream_));
+  }
+  void download(void* d, const void* s, size_t b) override {
+    if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToHost, stream_));
+    HIP_OK(hipStreamSynchronize(stream_));
+  }
+  void zero(void* p, size_t b) override {
+    if (b) HIP_OK(hipMemsetAsync(p, 0, b, stream_));
+  }
+  void copy_d2d(void* d, const void* s, size_t b) override {
+    if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, stream_));
+  }
+  void* prepare(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc) override {
+    auto* P = new Prepared();
+    P->da = da;
+    P->db = db;
+    P->dc = dc;
+    P->mode = (da == DT_F64) ? DT_F64 : (da == DT_F32 ? DT_F32 : DT_BF16);
+    std::vector<int> tiles;
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      const int tm = (jobs[j].m + TM - 1) / TM, tn = (jobs[j].n + TN - 1) / TN;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b) {
+          tiles.push_back((int)j);
+          tiles.push_back(a);
+          tiles.push_back(b);
+        }
+    }
+    P->ntiles = (long long)tiles.size() / 3;
+    if (P->ntiles) {
+      P->d_jobs = (RawJob*)alloc(jobs.size() * sizeof(RawJob));
+      P->d_terms = (RawTerm*)alloc(std::max<size_t>(terms.size(), 1) * sizeof(RawTerm));
+      P->d_tiles = (int*)alloc(tiles.size() * sizeof(int));
+      upload(P->d_jobs, jobs.data(), jobs.size() * sizeof(RawJob));
+      if (!terms.empty()) upload(P->d_terms, terms.data(), terms.size() * sizeof(RawTerm));
+      upload(P->d_tiles, tiles.data(), tiles.size() * sizeof(int));
+    }
+    pick(P->mode, da, db, dc);  // validate
+    return P;
+  }
+  void run(void* h) override {
+    auto* P = (Prepared*)h;
+    if (!P->ntiles) return;
+    KernelFn k = pick(P->mode, P->da, P->db, P->dc);
+    const long long maxg = 0x7fffffffLL;
+    for (long long t0 = 0; t0 < P->ntiles; t0 += maxg) {
+      const long long nt = std::min(maxg, P->ntiles - t0);
+      hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_tiles + 3 * t0);
+    }
+    HIP_OK(hipGetLastError());
+  }
+  void drop(void* h) override {
+    auto* P = (Prepared*)h;
+    if (!P) return;
+    HIP_OK(hipStreamSynchronize(stream_));
+    release(P->d_jobs);
+    release(P->d_terms);
+    release(P->d_tiles);
+    delete P;
+  }
+  void sync() override { HIP_OK(hipStreamSynchronize(stream_)); }
+  void convert(void* dst, int dd, const void* src, int ds, size_t n) override {
+    if (!n) return;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+#define C_(S, D) \
+  if (ds == S && dd == D) { hipLaunchKernelGGL((convert_kernel<S, D>), dim3(grid), dim3(256), 0, stream_, dst, src, (long long)n); HIP_OK(hipGetLastError()); return; }
+    C_(DT_F64, DT_F32) C_(DT_F64, DT_BF16) C_(DT_F32, DT_F64) C_(DT_BF16, DT_F64) C_(DT_F32, DT_BF16) C_(DT_BF16, DT_F32)
+#undef C_
+    throw std::runtime_error("executor: unsupported conversion");
+  }
+  hipStream_t stream() const { return stream_; }
+
+ private:
+  hipStream_t stream_ = nullptr;
+};
+
+}  // namespace
+
+Executor* make_hip_executor() { return new HipExec(); }
+
+}  // namespace dmrg

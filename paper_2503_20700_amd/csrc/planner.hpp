@@ -1,0 +1,249 @@
+// Host planner for spin-adapted two-site DMRG: symmetry sectors, operator
+// blocks ("environments"), their growth by one site, and the task lists of the
+// Davidson matrix-vector product H*psi.
+//
+// Hamiltonian (Sec. "Complete active space SCF", with the standard pairing and
+// factor 1/2 on the two-electron term):
+//   H = sum h_pq E_pq + 1/2 sum (pq|rs) sum_st a+_ps a+_rt a_st a_qs.
+// Orbitals are split at a cut into a left part X and a right part Y.  The
+// cross terms are written with normal operators on X and complementary
+// operators (integrals already summed in) on Y, or the reverse for the 3+1
+// split, so that their number grows like |X|^2:
+//   pair     sum_{i<=j in X} ap_S [A^S_ij (x) P^S_ij]^0 + h.c.
+//   B-Q      sum_{i,j in X}  [B^k_ij (x) Q^k_ij]^0,  Q = ee J - ex K
+//   1+3      sum_{p in X}    cs [C_p (x) SR_p]^0 + h.c.
+//   3+1      sum_{r in Y}    sc [SL_r (x) C_r]^0 + h.c.
+// with A^S_ij = [c_i c_j]^S, B^k_ij = [c_i d_j]^k, P^S_ij = 1/2 sum g_iqjs [d_s d_q]^S,
+// J_ij = sum g_ijrs [c_r d_s]^0, K^k_ij = sum g_iqrj [c_r d_q]^k,
+// SR_p = sum h_pq d_q + sum g_pqrs U(r,s,q), SL_r = sum g_pqrs T(p,q,s).
+//
+// Left blocks (sites 0..b-1) store H, C, D, A^S, Abar^S = [d d]^S, B^k and SL_r
+// (r >= b); right blocks (sites b..n-1) store H, C, D, P^S, J, K^k and SR_p
+// (p < b).  All operators are reduced (Wigner-Eckart) block-sparse matrices
+// over the bond's (N, 2S) sectors, in the convention
+//   <j m| T^k_q |j' m'> = <j' m'; k q | j m> <j||T||j'>.
+#pragma once
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "exec.hpp"
+#include "spin.hpp"
+
+namespace dmrg {
+
+struct Sector {
+  int n = 0, s2 = 0, dim = 0;
+};
+
+struct Bond {
+  std::vector<Sector> secs;
+  int find(int n, int s2) const;
+};
+
+struct OpBlock {
+  int bra = 0, ket = 0;
+  int64_t off = 0;
+};
+
+struct OpLayout {
+  int k2 = 0, dn = 0, nsec = 0;
+  std::vector<OpBlock> blocks;
+  std::vector<int> lookup;  // bra * nsec + ket -> block index, -1 if absent
+  int64_t size = 0;
+  int find(int bra, int ket) const {
+    if (bra < 0 || ket < 0) return -1;
+    return lookup[(size_t)bra * nsec + ket];
+  }
+};
+
+enum Fam : int {
+  F_H = 0, F_C, F_D, F_A0, F_A1, F_AB0, F_AB1, F_B0, F_B1, F_SL,
+  F_P0, F_P1, F_J, F_K0, F_K1, F_SR, kNumFam,
+  F_ID = 1000,      // identity operator
+  F_TMP0 = 2000     // F_TMP0 + t : temporary (linear-combination) family t
+};
+int fam_k2(int f);
+int fam_dn(int f);
+const char* fam_name(int f);
+
+struct Ref {
+  int fam = F_ID;
+  int idx = 0;
+  bool operator<(const Ref& o) const { return fam != o.fam ? fam < o.fam : idx < o.idx; }
+  bool operator==(const Ref& o) const { return fam == o.fam && idx == o.idx; }
+  bool is_id() const { return fam == F_ID; }
+};
+
+struct Family {
+  int k2 = 0, dn = 0;
+  const OpLayout* lay = nullptr;
+  int nops = 0;
+  int buf = -1;              // device buffer holding nops * lay->size values
+  std::vector<int> index;    // key -> op index (-1 absent); key = i or i*n + j
+};
+
+struct DevBuf {
+  int64_t n = 0;       // elements
+  void* p[4] = {nullptr, nullptr, nullptr, nullptr};  // per dtype copy
+};
+
+class Context;
+
+struct Block {
+  bool left = true;
+  int b = 0, n = 0;
+  Bond bond;
+  std::map<std::pair<int, int>, std::unique_ptr<OpLayout>> layouts;
+  Family fam[kNumFam];
+  std::vector<Family> tmp;
+  const OpLayout& layout(int k2, int dn);
+  const Family& family(int f) const { return f >= F_TMP0 ? tmp[f - F_TMP0] : fam[f]; }
+  int op(int f, int i, int j = -1) const;  // op index or -1
+  int64_t bytes_f64() const;
+};
+
+// One term of an operator on (block (x) site): coef * [L (x) s]^k (left growth)
+struct LAtom {
+  double c = 1.0;
+  Ref L;
+  int sop = S_I;
+  int kL2 = 0, ks2 = 0;
+  bool hc = false;  // apply the transpose (scalar targets only)
+};
+// One term of an operator on (site (x) block): coef * [s (x) R]^k (right growth)
+struct RAtom {
+  double c = 1.0;
+  int sop = S_I;
+  Ref R;
+  int ks2 = 0, kR2 = 0;
+  bool hc = false;
+};
+// One term of the two-site Hamiltonian: coef * [[L (x) s1]^kX (x) [s2 (x) R]^kX]^0
+struct Term4 {
+  double c = 1.0;
+  Ref L;
+  int s1 = S_I, kL2 = 0, k12 = 0, kX2 = 0;
+  int s2 = S_I, k22 = 0, kR2 = 0;
+  Ref R;
+  bool hc = false;
+};
+
+struct Integrals {
+  int n = 0;
+  std::vector<double> h, g;
+  double e_core = 0.0;
+  double H(int p, int q) const { return h[(size_t)p * n + q]; }
+  double G(int p, int q, int r, int s) const { return g[(((size_t)p * n + q) * n + r) * n + s]; }
+};
+
+// Site tensor of the MPS held on the device (FP64), with block offsets.
+struct SiteTensor {
+  bool left = true;  // A: (l, sigma, a) ; B: (c, sigma, r)
+  int j = 0;
+  struct Blk {
+    int s0, sig, s1;
+    int64_t off;
+    int rows, cols;
+  };
+  std::vector<Blk> blocks;
+  std::map<std::tuple<int, int, int>, int> find;
+  int buf = -1;
+};
+
+// Two-site wavefunction layout (super-blocks, see the ABI header).
+struct PsiLayout {
+  struct Row {
+    int il, s1, r0, dl;
+  };
+  struct Col {
+    int s2, ir, c0, dr;
+  };
+  struct SB {
+    int an, as2, cn, cs2, nrows, ncols;
+    int64_t off;
+    std::vector<Row> rows;
+    std::vector<Col> cols;
+  };
+  std::vector<SB> sbs;
+  int64_t size = 0;
+  void build(const Bond& lb, const Bond& rb, int n_elec, int two_s);
+};
+
+// Everything H*psi needs at one two-site position, prepared once per position.
+struct HpsiPlan {
+  int k = -1;
+  PsiLayout lay;
+  std::vector<Term4> terms;
+  // chunks of terms: stage L then stage R batches (symbolic)
+  struct Chunk {
+    GemmBatch stageL, stageR;
+    int64_t xsize = 0;
+  };
+  std::vector<Chunk> chunks;
+  GemmBatch diag;   // diagonal of H_eff, accumulated into the diag buffer
+  double flops = 0.0;
+  int64_t xmax = 0;
+  size_t n_stage_terms = 0;
+};
+
+class Context {
+ public:
+  Context(Executor* ex, const Integrals& ints, int n_elec, int two_s);
+  ~Context();
+  Executor* ex;
+  Integrals I;
+  int n_elec, two_s;
+  std::vector<SiteOp> sops;        // fixed site ops followed by per-orbital site Hamiltonians
+  int site_h(int o) const { return kNumFixedSite + o; }
+
+  // device buffer registry
+  std::vector<DevBuf> bufs;
+  int new_buf(int64_t n);           // FP64 buffer, zeroed
+  void free_buf(int id);
+  void* ptr(int buf, int dt = DT_F64) const { return bufs[buf].p[dt]; }
+  void ensure_dtype(int buf, int dt);  // create converted copy from the F64 master
+  void alloc_dtype(int buf, int dt);   // storage in dtype dt, contents undefined
+  int ph[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // placeholder buffers (-1..-7) of the current plan
+
+  // MPS
+  int n = 0, k = -1;
+  std::vector<Bond> bonds;                 // bonds 0..n (left QNs up to k, right QNs from k+2)
+  std::vector<SiteTensor> sites;           // size n (entries k, k+1 unused)
+  std::unique_ptr<Block> Lblk, Rblk;       // blocks at bonds k and k+2
+  std::vector<std::unique_ptr<Block>> Lhist;  // left blocks kept per bond (optional)
+
+  // building
+  std::unique_ptr<Block> vacuum_left();
+  std::unique_ptr<Block> vacuum_right();
+  std::unique_ptr<Block> grow_left(Block& L, const SiteTensor& A, const Bond& newbond);
+  std::unique_ptr<Block> grow_right(Block& R, const SiteTensor& B, const Bond& newbond);
+  void free_block(Block& blk);
+
+  // operator expressions
+  std::vector<LAtom> lgrow(const Block& L, int f, int i, int j) const;
+  std::vector<RAtom> rgrow(const Block& R, int f, int i, int j) const;
+  std::vector<LAtom> lgrow_h(const Block& L) const;
+  std::vector<RAtom> rgrow_h(const Block& R) const;
+
+  // H*psi
+  std::unique_ptr<HpsiPlan> plan_hpsi(int64_t x_budget_elems);
+  std::vector<Term4> hpsi_terms(Block& L, Block& R);
+
+  // linear combinations -> temporary families on a block
+  Ref make_lincomb(Block& blk, int k2, int dn, const std::vector<std::pair<Ref, double>>& parts,
+                   std::vector<std::vector<std::pair<Ref, double>>>* pending, std::vector<int>* pending_fam);
+  void materialise_lincombs(Block& blk, const std::vector<std::vector<std::pair<Ref, double>>>& pending,
+                            const std::vector<int>& pending_fam);
+
+  // resolve a symbolic batch to raw pointers (A/B/C dtypes per buffer role)
+  void resolve(const GemmBatch& b, std::vector<RawJob>& jobs, std::vector<RawTerm>& terms, int dta, int dtb,
+               int dtc) const;
+  void run_batch(const GemmBatch& b, int dta = DT_F64, int dtb = DT_F64, int dtc = DT_F64);
+
+  double last_flops = 0.0;
+  int64_t bytes_in_use = 0, peak_bytes = 0;
+};
+
+}  // namespace dmrg

@@ -1,0 +1,132 @@
+// Per-context state behind the C ABI: executor, planner context, the H*psi
+// plan of the current two-site block and its device buffers.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "../../include/dmrg.h"
+#include "planner.hpp"
+
+// psi_in, psi_out, X, ones, diag placeholders used by the H*psi task lists
+enum { PH_IN = 1, PH_OUT = 2, PH_X = 3, PH_ONES = 4, PH_DIAG = 5 };
+
+struct dmrg_ctx {
+  dmrg_opts opts{};
+  std::unique_ptr<dmrg::Executor> ex;
+  std::unique_ptr<dmrg::Context> C;
+  std::unique_ptr<dmrg::HpsiPlan> plan;
+  int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1;
+  struct Prepared {
+    std::vector<void*> L, R;
+    bool ready = false;
+  };
+  Prepared prep[3];
+  // cut spectrum of the last truncation
+  std::vector<double> cut_values;
+  std::vector<int> cut_spins;
+
+  ~dmrg_ctx() {
+    reset_plan();
+    C.reset();
+    ex.reset();
+  }
+
+  int64_t budget() const {
+    return opts.work_budget_elems > 0 ? (int64_t)opts.work_budget_elems : ((int64_t)1 << 30);
+  }
+
+  void reset_plan() {
+    for (auto& p : prep) {
+      for (void* h : p.L) ex->drop(h);
+      for (void* h : p.R) ex->drop(h);
+      p.L.clear();
+      p.R.clear();
+      p.ready = false;
+    }
+    if (C) {
+      for (int b : {b_in, b_out, b_x, b_ones, b_diag}) C->free_buf(b);
+      if (C->Lblk) {
+        for (auto& t : C->Lblk->tmp) C->free_buf(t.buf);
+        C->Lblk->tmp.clear();
+      }
+      if (C->Rblk) {
+        for (auto& t : C->Rblk->tmp) C->free_buf(t.buf);
+        C->Rblk->tmp.clear();
+      }
+    }
+    b_in = b_out = b_x = b_ones = b_diag = -1;
+    plan.reset();
+  }
+
+  void bind() {
+    C->ph[PH_IN] = b_in;
+    C->ph[PH_OUT] = b_out;
+    C->ph[PH_X] = b_x;
+    C->ph[PH_ONES] = b_ones;
+    C->ph[PH_DIAG] = b_diag;
+  }
+
+  void ensure_plan() {
+    if (plan) return;
+    plan = C->plan_hpsi(budget());
+    const int64_t n = plan->lay.size;
+    b_in = C->new_buf(std::max<int64_t>(n, 1));
+    b_out = C->new_buf(std::max<int64_t>(n, 1));
+    b_x = C->new_buf(std::max<int64_t>(plan->xmax, 1));
+    b_diag = C->new_buf(std::max<int64_t>(n, 1));
+    int maxd = 1;
+    for (auto& bd : C->bonds)
+      for (auto& s : bd.secs) maxd = std::max(maxd, s.dim);
+    std::vector<double> ones((size_t)maxd, 1.0);
+    b_ones = C->new_buf(maxd);
+    ex->upload(C->ptr(b_ones), ones.data(), ones.size() * 8);
+    bind();
+    C->run_batch(plan->diag);
+  }
+
+  static int op_dt(int prec) { return prec == DMRG_FP64 ? dmrg::DT_F64 : prec == DMRG_FP32 ? dmrg::DT_F32 : dmrg::DT_BF16; }
+  static int out_dt(int prec) { return prec == DMRG_FP64 ? dmrg::DT_F64 : dmrg::DT_F32; }
+
+  void prepare(int prec) {
+    Prepared& P = prep[prec];
+    if (P.ready) return;
+    const int od = op_dt(prec), xd = op_dt(prec), outd = out_dt(prec);
+    if (od != dmrg::DT_F64) {
+      for (dmrg::Block* blk : {C->Lblk.get(), C->Rblk.get()}) {
+        for (int f = 0; f < dmrg::kNumFam; ++f)
+          if (blk->fam[f].buf >= 0) C->ensure_dtype(blk->fam[f].buf, od);
+        for (auto& t : blk->tmp)
+          if (t.buf >= 0) C->ensure_dtype(t.buf, od);
+      }
+      C->alloc_dtype(b_in, od);
+      C->alloc_dtype(b_x, xd);
+      C->alloc_dtype(b_out, outd);
+    }
+    bind();
+    for (auto& ch : plan->chunks) {
+      std::vector<dmrg::RawJob> j;
+      std::vector<dmrg::RawTerm> t;
+      C->resolve(ch.stageL, j, t, od, od, xd);
+      P.L.push_back(ex->prepare(j, t, od, od, xd));
+      C->resolve(ch.stageR, j, t, xd, od, outd);
+      P.R.push_back(ex->prepare(j, t, xd, od, outd));
+    }
+    P.ready = true;
+  }
+
+  // psi_out = H psi_in on the device buffers b_in / b_out (FP64 masters).
+  void hpsi_device(int prec) {
+    prepare(prec);
+    const int64_t n = plan->lay.size;
+    const int od = op_dt(prec), outd = out_dt(prec);
+    if (od != dmrg::DT_F64) ex->convert(C->ptr(b_in, od), od, C->ptr(b_in), dmrg::DT_F64, (size_t)n);
+    ex->zero(C->ptr(b_out, outd), (size_t)n * dmrg::dtype_size(outd));
+    Prepared& P = prep[prec];
+    for (size_t i = 0; i < P.L.size(); ++i) {
+      ex->run(P.L[i]);
+      ex->run(P.R[i]);
+    }
+    if (outd != dmrg::DT_F64) ex->convert(C->ptr(b_out), dmrg::DT_F64, C->ptr(b_out, outd), outd, (size_t)n);
+    ex->sync();
+  }
+};

@@ -1,0 +1,49 @@
+"""The grouped MFMA GEMM kernel on its own (through dmrg_gemm_selftest) against
+numpy's matmul: tile interiors, ragged tails in m, n and k, transposed
+operands, identity operands, accumulation, and the three arithmetic paths."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 1, 1), (16, 16, 4), (64, 64, 16), (65, 63, 17), (130, 70, 33), (7, 200, 129), (200, 9, 5)]
+
+
+@pytest.mark.parametrize("m,n,k", SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_fp64(m, n, k, ta, tb):
+    from paper_2503_20700_amd.binding import gemm_selftest
+    rng = np.random.default_rng(m * 1000 + n * 10 + k)
+    a = rng.normal(size=(m, k))
+    b = rng.normal(size=(k, n))
+    c0 = rng.normal(size=(m, n))
+    got = gemm_selftest(a.T.copy() if ta else a, b.T.copy() if tb else b, C=c0, trans_a=bool(ta), trans_b=bool(tb),
+                        alpha=0.75, beta=1.0)
+    ref = c0 + 0.75 * (a @ b)
+    assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (65, 63), (130, 7)])
+def test_gemm_identity_operands(m, n):
+    from paper_2503_20700_amd.binding import gemm_selftest
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=(m, n))
+    got = gemm_selftest(None, b, ident_a=True, alpha=-2.0)
+    assert np.abs(got + 2.0 * b).max() < 1e-14
+    a = rng.normal(size=(m, n))
+    got = gemm_selftest(a.T.copy(), None, trans_a=True, ident_b=True, alpha=0.5)
+    assert np.abs(got - 0.5 * a).max() < 1e-14
+
+
+@pytest.mark.parametrize("prec,eps", [(1, 2.0 ** -24), (2, 2.0 ** -8)])
+@pytest.mark.parametrize("m,n,k", [(65, 63, 17), (130, 70, 300)])
+def test_gemm_low_precision(prec, eps, m, n, k):
+    from paper_2503_20700_amd.binding import gemm_selftest
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=(m, k))
+    b = rng.normal(size=(k, n))
+    got = gemm_selftest(a, b, prec=prec)
+    ref = a @ b
+    # |error| <= ~2 eps * sum_k |a||b| (operand rounding) + k * 2^-24 * ... (fp32 accumulation)
+    bound = (2 * eps + k * 2.0 ** -24) * (np.abs(a) @ np.abs(b))
+    assert np.all(np.abs(got - ref) <= 4 * bound + 1e-30)
