@@ -130,6 +130,11 @@ int dmrg_cut_spectrum(dmrg_ctx *c, double *values, int *two_s, int *n, int capac
  * out[4] = number of block-product tasks per H*psi. */
 int dmrg_stats(dmrg_ctx *c, double *out, int n);
 
+/* Device-event timing of the library's GEMM launches on its own stream.
+ * mode 1: clear and start recording; 0: report and stop; -1: report only.
+ * ms / launches (nullable) receive the summed kernel time and launch count. */
+int dmrg_kernel_timing(dmrg_ctx *c, int mode, double *ms, long long *launches);
+
 /* Kernel self-test: C (m x n) = beta*C + alpha * op(A) op(B) through the same
  * grouped MFMA kernel the hot path uses (host FP64 buffers; A is m x k or,
  * with trans_a, k x m row-major; B is k x n or n x k).  ident_a / ident_b

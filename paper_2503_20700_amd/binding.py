@@ -60,6 +60,7 @@ def load(path=None):
         "dmrg_cut_spectrum": (I, [P, dp, ip, ip, I]),
         "dmrg_stats": (I, [P, dp, I]),
         "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
+        "dmrg_kernel_timing": (I, [P, I, dp, llp]),
         "dmrg_last_error": (ct.c_char_p, []),
         "dmrg_destroy": (V, [P]),
     }
@@ -74,7 +75,7 @@ def load(path=None):
 def exported_symbols():
     return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_heff_diag",
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
-            "dmrg_last_error", "dmrg_destroy"]
+            "dmrg_kernel_timing", "dmrg_last_error", "dmrg_destroy"]
 
 
 def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ident_b=False, alpha=1.0, beta=0.0,
@@ -192,6 +193,11 @@ class DMRG:
         self._check(self.lib.dmrg_cut_spectrum(self._h, _dp(vals), spins.ctypes.data_as(ct.POINTER(ct.c_int)),
                                                ct.byref(n), capacity))
         return vals[:n.value].copy(), spins[:n.value].copy()
+
+    def kernel_timing(self, mode):
+        ms, n = ct.c_double(), ct.c_longlong()
+        self._check(self.lib.dmrg_kernel_timing(self._h, mode, ct.byref(ms), ct.byref(n)))
+        return ms.value, n.value
 
     def stats(self):
         out = np.zeros(5)

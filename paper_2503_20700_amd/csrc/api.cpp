@@ -1,6 +1,9 @@
 // C ABI: argument validation, MPS ingestion, operator-block build and the
 // H*psi driver.  See include/dmrg.h for the contract.
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -131,17 +134,27 @@ extern "C" int dmrg_set_mps(dmrg_ctx* c, int k, const int* bs, const int* counts
     }
     C.sites = std::move(sites);
     // ---- operator blocks
+    const bool verbose = std::getenv("DMRG_VERBOSE") != nullptr;
+    auto t_start = std::chrono::steady_clock::now();
+    auto progress = [&](const char* side, int b, const Block& blk) {
+      if (!verbose) return;
+      double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      std::fprintf(stderr, "[dmrg] %s block at bond %d: %.2f GB, %.1f s\n", side, b, blk.bytes_f64() / 1e9, s);
+      std::fflush(stderr);
+    };
     auto L = C.vacuum_left();
     for (int j = 0; j < k; ++j) {
       auto N = C.grow_left(*L, C.sites[j], C.bonds[j + 1]);
       C.free_block(*L);
       L = std::move(N);
+      progress("left", j + 1, *L);
     }
     auto R = C.vacuum_right();
     for (int j = n - 1; j >= k + 2; --j) {
       auto N = C.grow_right(*R, C.sites[j], C.bonds[j]);
       C.free_block(*R);
       R = std::move(N);
+      progress("right", j, *R);
     }
     C.Lblk = std::move(L);
     C.Rblk = std::move(R);
@@ -216,6 +229,23 @@ extern "C" int dmrg_heff_diag(dmrg_ctx* c, int k, double* diag) {
     return DMRG_OK;
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_heff_diag: ") + e.what());
+  }
+}
+
+extern "C" int dmrg_kernel_timing(dmrg_ctx* c, int mode, double* ms, long long* launches) {
+  if (!c) return fail(DMRG_ERR_ARG, "dmrg_kernel_timing: null context");
+  try {
+    if (mode == 1) {
+      c->ex->timing(true);
+    } else {
+      auto kt = c->ex->kernel_time();
+      if (ms) *ms = kt.first;
+      if (launches) *launches = kt.second;
+      if (mode == 0) c->ex->timing(false);
+    }
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_kernel_timing: ") + e.what());
   }
 }
 

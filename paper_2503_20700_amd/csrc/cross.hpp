@@ -70,13 +70,56 @@ struct StoredRightProv {
     if (idx < 0 || c == 0.0) return {};
     return {{c, Ref{f, idx}}};
   }
+  const Integrals* I = nullptr;  // needed when R holds normal pairs
+  // Complementary pair operators written over the normal pairs of R:
+  //   P^S_ij = 1/2 sum_{s,q in R} g_iqjs [d_s d_q]^S,  J_ij = sum g_ijrs [c_r d_s]^0,
+  //   K^k_ij = sum g_iqrj [c_r d_q]^k.
+  Expr<Ref> Pn(int S, int i, int j) const {
+    Expr<Ref> e;
+    for (int s = R.b; s < R.n; ++s)
+      for (int q = R.b; q < R.n; ++q) {
+        if (S == 1 && s == q) continue;
+        const double sg = (s > q && S == 1) ? -1.0 : 1.0;
+        const double c = 0.5 * sg * I->G(i, q, j, s);
+        if (c == 0.0) continue;
+        const int f = S ? F_AB1 : F_AB0;
+        int idx = R.op(f, std::min(s, q), std::max(s, q));
+        if (idx >= 0) e.push_back({c, Ref{f, idx}});
+      }
+    return e;
+  }
+  Expr<Ref> Jn(int i, int j) const {
+    Expr<Ref> e;
+    for (int r = R.b; r < R.n; ++r)
+      for (int s = R.b; s < R.n; ++s) {
+        const double c = I->G(i, j, r, s);
+        int idx = R.op(F_B0, r, s);
+        if (c != 0.0 && idx >= 0) e.push_back({c, Ref{F_B0, idx}});
+      }
+    return e;
+  }
+  Expr<Ref> Kn(int k, int i, int j) const {
+    Expr<Ref> e;
+    const int f = k ? F_B1 : F_B0;
+    for (int r = R.b; r < R.n; ++r)
+      for (int q = R.b; q < R.n; ++q) {
+        const double c = I->G(i, q, r, j);
+        int idx = R.op(f, r, q);
+        if (c != 0.0 && idx >= 0) e.push_back({c, Ref{f, idx}});
+      }
+    return e;
+  }
+  static Expr<Ref> scaled(Expr<Ref> e, double s) {
+    for (auto& x : e) x.first *= s;
+    return e;
+  }
   Expr<Ref> C(int r) const { return one(F_C, r); }
-  Expr<Ref> P(int S, int i, int j) const { return one(S ? F_P1 : F_P0, i, j); }
+  Expr<Ref> P(int S, int i, int j) const { return R.normal ? Pn(S, i, j) : one(S ? F_P1 : F_P0, i, j); }
   Expr<Ref> Q(int k, int i, int j) const {
     const SpinConstants& sc = spin_constants();
-    Expr<Ref> e = one(k ? F_K1 : F_K0, i, j, -sc.ex[k]);
+    Expr<Ref> e = R.normal ? scaled(Kn(k, i, j), -sc.ex[k]) : one(k ? F_K1 : F_K0, i, j, -sc.ex[k]);
     if (k == 0) {
-      auto jj = one(F_J, std::min(i, j), std::max(i, j), sc.ee[0]);
+      auto jj = R.normal ? scaled(Jn(i, j), sc.ee[0]) : one(F_J, std::min(i, j), std::max(i, j), sc.ee[0]);
       e.insert(e.end(), jj.begin(), jj.end());
     }
     return e;

@@ -84,6 +84,21 @@ class Executor {
   virtual void run(void* handle) = 0;
   virtual void drop(void* handle) = 0;
   virtual void sync() = 0;
+  // ---- FP64 vector primitives for the Davidson iteration (device arrays)
+  // out_host[i] = <V_i, w>, V_i = V + i*ldv, i < m (m <= 64); fixed summation order
+  virtual void multidot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out_host) = 0;
+  // y = beta*y + sum_i c_host[i] * V_i   (m <= 64)
+  virtual void combine(double* y, const double* V, int64_t ldv, int m, const double* c_host, int64_t n,
+                       double beta) = 0;
+  // z = a*x + b*y
+  virtual void axpby(double* z, double a, const double* x, double b, const double* y, int64_t n) = 0;
+  // t_i = r_i / (theta - d_i), with |theta - d_i| floored at eps
+  virtual void precond(double* t, const double* r, const double* d, double theta, double eps, int64_t n) = 0;
+  // Per-launch timing of run() with device events on the executor's stream.
+  // kernel_time() synchronises and returns (total ms, launches) since the
+  // last call to timing(true).
+  virtual void timing(bool on) { (void)on; }
+  virtual std::pair<double, long long> kernel_time() { return {0.0, 0}; }
   // element-wise precision conversion of n values
   virtual void convert(void* dst, int dt_dst, const void* src, int dt_src, size_t n) = 0;
 };

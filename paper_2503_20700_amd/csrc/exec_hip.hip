@@ -67,6 +67,15 @@ __device__ __forceinline__ void stv(void* p, long long i, V v) {
   else ((u16*)p)[i] = f2bf((float)v);
 }
 
+// Row of accumulator element v held by lane group lg (= lane / 16) inside a
+// 16x16 MFMA output block; the column is lane % 16.  The FP64 instruction
+// interleaves rows across lane groups, the FP32-accumulating ones do not.
+template <int MODE>
+__device__ __forceinline__ int acc_row(int lg, int v) {
+  if constexpr (MODE == DT_F64) return 4 * v + lg;
+  else return 4 * lg + v;
+}
+
 // MODE: DT_F64 / DT_F32 / DT_BF16 arithmetic; DA/DB/DC storage types.
 template <int MODE, int DA, int DB, int DC>
 __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms,
@@ -111,7 +120,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
         for (int b = 0; b < 2; ++b)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int row = m0 + wm + a * 16 + 4 * lg + v;
+            const int row = m0 + wm + a * 16 + acc_row<MODE>(lg, v);
             const int col = n0 + wn + b * 16 + lr;
             if (row < J.m && col < J.n) {
               const long long idx = tr ? (long long)col * ld + row : (long long)row * ld + col;
@@ -200,7 +209,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm + a * 16 + 4 * lg + v;
+        const int row = m0 + wm + a * 16 + acc_row<MODE>(lg, v);
         const int col = n0 + wn + b * 16 + lr;
         if (row < J.m && col < J.n) {
           const long long o = (long long)row * J.ldc + col;
@@ -218,6 +227,72 @@ template <int DS, int DD>
 __global__ void convert_kernel(void* dst, const void* src, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     stv<DD>(dst, i, ldv<DS>(src, i));
+}
+
+// ---- FP64 vector kernels (Davidson).  Grid-stride loops, fixed reduction order.
+constexpr int kDotBlocks = 1024;
+
+__global__ __launch_bounds__(256) void multidot_partial(const double* __restrict__ V, long long ldv, int m,
+                                                         const double* __restrict__ w, long long n,
+                                                         double* __restrict__ part) {
+  __shared__ double red[256];
+  const long long chunk = (n + gridDim.x - 1) / gridDim.x;
+  const long long lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+  for (int i = 0; i < m; ++i) {
+    double s = 0.0;
+    for (long long j = lo + threadIdx.x; j < hi; j += blockDim.x) s += V[i * ldv + j] * w[j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)i * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void multidot_final(const double* __restrict__ part, int nb, int m,
+                                                       double* __restrict__ out) {
+  __shared__ double red[256];
+  for (int i = 0; i < m; ++i) {
+    double s = 0.0;
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) s += part[(long long)i * nb + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = red[0];
+    __syncthreads();
+  }
+}
+
+struct Coef64 {
+  double c[64];
+};
+
+__global__ void combine_kernel(double* __restrict__ y, const double* __restrict__ V, long long ldv, int m, Coef64 c,
+                               long long n, double beta) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n; j += (long long)gridDim.x * blockDim.x) {
+    double s = (beta == 0.0) ? 0.0 : beta * y[j];
+    for (int i = 0; i < m; ++i) s += c.c[i] * V[i * ldv + j];
+    y[j] = s;
+  }
+}
+
+__global__ void axpby_kernel(double* z, double a, const double* x, double b, const double* y, long long n) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n; j += (long long)gridDim.x * blockDim.x)
+    z[j] = a * x[j] + b * y[j];
+}
+
+__global__ void precond_kernel(double* t, const double* r, const double* d, double theta, double eps, long long n) {
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n; j += (long long)gridDim.x * blockDim.x) {
+    double den = theta - d[j];
+    if (fabs(den) < eps) den = den < 0 ? -eps : eps;
+    t[j] = r[j] / den;
+  }
 }
 
 struct Prepared {
@@ -245,7 +320,13 @@ class HipExec : public Executor {
  public:
   HipExec() { HIP_OK(hipStreamCreate(&stream_)); }
   ~HipExec() override {
-    if (stream_) hipStreamDestroy(stream_);
+    if (dot_part_) (void)hipFree(dot_part_);
+    if (dot_out_) (void)hipFree(dot_out_);
+    for (auto& e : events_) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    if (stream_) (void)hipStreamDestroy(stream_);
   }
   void* alloc(size_t bytes) override {
     void* p = nullptr;
@@ -305,11 +386,40 @@ class HipExec : public Executor {
     if (!P->ntiles) return;
     KernelFn k = pick(P->mode, P->da, P->db, P->dc);
     const long long maxg = 0x7fffffffLL;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timing_) {
+      HIP_OK(hipEventCreate(&e0));
+      HIP_OK(hipEventCreate(&e1));
+      HIP_OK(hipEventRecord(e0, stream_));
+    }
     for (long long t0 = 0; t0 < P->ntiles; t0 += maxg) {
       const long long nt = std::min(maxg, P->ntiles - t0);
       hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_tiles + 3 * t0);
     }
     HIP_OK(hipGetLastError());
+    if (timing_) {
+      HIP_OK(hipEventRecord(e1, stream_));
+      events_.push_back({e0, e1});
+    }
+  }
+  void timing(bool on) override {
+    sync();
+    for (auto& e : events_) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    events_.clear();
+    timing_ = on;
+  }
+  std::pair<double, long long> kernel_time() override {
+    sync();
+    double tot = 0.0;
+    for (auto& e : events_) {
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, e.first, e.second));
+      tot += ms;
+    }
+    return {tot, (long long)events_.size()};
   }
   void drop(void* h) override {
     auto* P = (Prepared*)h;
@@ -330,10 +440,45 @@ class HipExec : public Executor {
 #undef C_
     throw std::runtime_error("executor: unsupported conversion");
   }
+  void multidot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out_host) override {
+    if (m <= 0) return;
+    if (m > 64) throw std::runtime_error("multidot: m > 64");
+    if (!dot_part_) {
+      dot_part_ = (double*)alloc(sizeof(double) * kDotBlocks * 64);
+      dot_out_ = (double*)alloc(sizeof(double) * 64);
+    }
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (n + 255) / 256));
+    hipLaunchKernelGGL(multidot_partial, dim3(nb), dim3(256), 0, stream_, V, (long long)ldv, m, w, (long long)n,
+                       dot_part_);
+    hipLaunchKernelGGL(multidot_final, dim3(1), dim3(256), 0, stream_, dot_part_, nb, m, dot_out_);
+    HIP_OK(hipGetLastError());
+    download(out_host, dot_out_, sizeof(double) * m);
+  }
+  void combine(double* y, const double* V, int64_t ldv, int m, const double* c_host, int64_t n, double beta) override {
+    if (m > 64) throw std::runtime_error("combine: m > 64");
+    Coef64 c{};
+    for (int i = 0; i < m; ++i) c.c[i] = c_host[i];
+    hipLaunchKernelGGL(combine_kernel, dim3(grid1(n)), dim3(256), 0, stream_, y, V, (long long)ldv, m, c, (long long)n,
+                       beta);
+    HIP_OK(hipGetLastError());
+  }
+  void axpby(double* z, double a, const double* x, double b, const double* y, int64_t n) override {
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid1(n)), dim3(256), 0, stream_, z, a, x, b, y, (long long)n);
+    HIP_OK(hipGetLastError());
+  }
+  void precond(double* t, const double* r, const double* d, double theta, double eps, int64_t n) override {
+    hipLaunchKernelGGL(precond_kernel, dim3(grid1(n)), dim3(256), 0, stream_, t, r, d, theta, eps, (long long)n);
+    HIP_OK(hipGetLastError());
+  }
   hipStream_t stream() const { return stream_; }
 
  private:
+  static unsigned grid1(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+  double* dot_part_ = nullptr;
+  double* dot_out_ = nullptr;
   hipStream_t stream_ = nullptr;
+  bool timing_ = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events_;
 };
 
 }  // namespace

@@ -63,6 +63,7 @@ struct MKey {
 std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
   Block& L = *Lblk;
   Block& R = *Rblk;
+  to_complementary(R);  // the middle cut pairs normal operators on the left with complementary ones on the right
   auto plan = std::make_unique<HpsiPlan>();
   plan->k = k;
   plan->lay.build(L.bond, R.bond, n_elec, two_s);

@@ -171,7 +171,10 @@ static void init_families(Context& C, Block& blk) {
     for (int q = b; q < n; ++q) k1.push_back({q, -1});
     for (int p = 0; p < b; ++p) kout.push_back({p, -1});
   }
-  const int lo = blk.left ? 0 : 0, hi = blk.left ? b : b;  // pair indices: inside (left) / outside (right)
+  // pair indices: inside the block (normal pair operators) or, for right
+  // blocks in complementary mode, the orbitals to the left of the block
+  const bool inside = blk.left || blk.normal;
+  const int lo = inside ? (blk.left ? 0 : b) : 0, hi = inside ? (blk.left ? b : n) : b;
   for (int i = lo; i < hi; ++i)
     for (int j = lo; j < hi; ++j) {
       kall.push_back({i, j});
@@ -181,7 +184,15 @@ static void init_families(Context& C, Block& blk) {
   add_family(C, blk, F_H, {{0, -1}});
   add_family(C, blk, F_C, k1);
   add_family(C, blk, F_D, k1);
-  if (blk.left) {
+  if (!blk.left && blk.normal) {
+    add_family(C, blk, F_A0, ksym);
+    add_family(C, blk, F_A1, kasym);
+    add_family(C, blk, F_AB0, ksym);
+    add_family(C, blk, F_AB1, kasym);
+    add_family(C, blk, F_B0, kall);
+    add_family(C, blk, F_B1, kall);
+    add_family(C, blk, F_SR, kout);
+  } else if (blk.left) {
     add_family(C, blk, F_A0, ksym);
     add_family(C, blk, F_A1, kasym);
     add_family(C, blk, F_AB0, ksym);
@@ -212,6 +223,7 @@ std::unique_ptr<Block> Context::vacuum_left() {
 std::unique_ptr<Block> Context::vacuum_right() {
   auto blk = std::make_unique<Block>();
   blk->left = false;
+  blk->normal = true;
   blk->b = n;
   blk->n = n;
   blk->bond.secs = {Sector{0, 0, 1}};
@@ -338,16 +350,48 @@ std::vector<RAtom> Context::rgrow(const Block& R, int f, int i, int j) const {
       add(1.0, S_I, op(F_SR, p), 0, 1);
       add(I.H(p, o), S_D, Ref{}, 1, 0);
       add(I.G(p, o, o, o), S_U3, Ref{}, 1, 0);
-      for (int S = 0; S < 2; ++S) add(2.0 * sc.u_q1[S], S_C, op(S ? F_P1 : F_P0, p, o), 1, 2 * S);
-      for (int k = 0; k < 2; ++k) add(sc.u_q2[k], S_D, op(k ? F_K1 : F_K0, p, o), 1, 2 * k);
-      add(sc.u_q3[0], S_D, op(F_J, p, o), 1, 0);
       if (std::fabs(sc.u_q3[1]) > 1e-14) throw std::runtime_error("rgrow: unexpected spin-1 Coulomb part");
+      if (!R.normal) {
+        for (int S = 0; S < 2; ++S) add(2.0 * sc.u_q1[S], S_C, op(S ? F_P1 : F_P0, p, o), 1, 2 * S);
+        for (int k = 0; k < 2; ++k) add(sc.u_q2[k], S_D, op(k ? F_K1 : F_K0, p, o), 1, 2 * k);
+        add(sc.u_q3[0], S_D, op(F_J, p, o), 1, 0);
+      } else {
+        // the same three parts with the integral sums over R done on normal pairs
+        for (int s = o + 1; s < n; ++s)
+          for (int q = o + 1; q < n; ++q) {
+            for (int S = 0; S < 2; ++S) {  // sum g_pqos [d_s d_q]^S
+              if (S == 1 && s == q) continue;
+              const double sg = (s > q && S == 1) ? -1.0 : 1.0;
+              add(sc.u_q1[S] * sg * I.G(p, q, o, s), S_C, op(S ? F_AB1 : F_AB0, std::min(s, q), std::max(s, q)), 1,
+                  2 * S);
+            }
+            for (int k = 0; k < 2; ++k)  // sum g_pqro [c_r d_q]^k, here r = s
+              add(sc.u_q2[k] * I.G(p, q, s, o), S_D, op(k ? F_B1 : F_B0, s, q), 1, 2 * k);
+            add(sc.u_q3[0] * I.G(p, o, s, q), S_D, op(F_B0, s, q), 1, 0);  // sum g_pors [c_r d_s]^0, r = s, s = q
+          }
+      }
       for (int k = 0; k < 2; ++k) {
         const int scd = k ? S_CD1 : S_CD0;
         for (int q = o + 1; q < n; ++q) add(sc.u_q4[k] * I.G(p, q, o, o), scd, op(F_D, q), 2 * k, 1);
         for (int s = o + 1; s < n; ++s) add(sc.u_q5[k] * I.G(p, o, o, s), scd, op(F_D, s), 2 * k, 1);
       }
       for (int r = o + 1; r < n; ++r) add(sc.u_q6[0] * I.G(p, o, r, o), S_DD0, op(F_C, r), 0, 1);
+      break;
+    }
+    case F_A0: case F_A1: case F_AB0: case F_AB1: {  // normal pairs inside (o (x) R), i <= j
+      const int S = (f == F_A1 || f == F_AB1) ? 1 : 0;
+      const bool cre = (f == F_A0 || f == F_A1);
+      if (i > o) add(1.0, S_I, op(f, i, j), 0, 2 * S);
+      else if (j > o) add(1.0, cre ? S_C : S_D, op(cre ? F_C : F_D, j), 1, 1);
+      else if (S == 0) add(1.0, cre ? S_CC0 : S_DD0, Ref{}, 0, 0);
+      break;
+    }
+    case F_B0: case F_B1: {
+      const int k = f == F_B1 ? 1 : 0;
+      if (i > o && j > o) add(1.0, S_I, op(f, i, j), 0, 2 * k);
+      else if (j > o) add(1.0, S_C, op(F_D, j), 1, 1);          // [c_o d_j]^k
+      else if (i > o) add(sc.cd_swap[k], S_D, op(F_C, i), 1, 1);  // [c_i d_o]^k
+      else add(1.0, k ? S_CD1 : S_CD0, Ref{}, 2 * k, 0);
       break;
     }
     default:
@@ -378,7 +422,7 @@ std::vector<RAtom> Context::rgrow_h(const Block& R) const {
   raw.push_back(RAtom{1.0, S_I, Ref{F_H, 0}, 0, 0, false});
   raw.push_back(RAtom{1.0, site_h(o), Ref{}, 0, 0, false});
   xterms::SiteLeftProv X{I, o};
-  xterms::StoredRightProv Y{R};
+  xterms::StoredRightProv Y{R, &I};
   xterms::cross_terms(X, Y, [&](double c, int px, const Ref& py, int k2, bool hc) {
     if (c != 0.0 && py.idx >= 0) raw.push_back(RAtom{c, px, py, k2, k2, hc});
   });
@@ -457,6 +501,83 @@ void Context::materialise_lincombs(Block& blk, const std::vector<std::vector<std
   }
   if (!batch.jobs.empty()) run_batch(batch);
   for (int cb : coef_bufs) free_buf(cb);
+}
+
+// Fill family `tf` of blk: op t = sum over rows[t] of coefficient * source op,
+// as one GEMM (coefficient matrix) x (source family buffer) per source family.
+static void lincomb_into_family(Context& C, Block& blk, int tf,
+                                const std::vector<std::vector<std::pair<Ref, double>>>& rows) {
+  Family& T = blk.fam[tf];
+  const int64_t size = T.lay->size;
+  if (size == 0 || T.nops == 0) return;
+  std::map<int, std::vector<double>> coef;
+  for (size_t r = 0; r < rows.size(); ++r)
+    for (auto& [ref, c] : rows[r]) {
+      const Family& S = blk.family(ref.fam);
+      if (S.lay != T.lay) throw std::runtime_error("lincomb_into_family: layout mismatch");
+      auto& m = coef[ref.fam];
+      if (m.empty()) m.assign((size_t)T.nops * S.nops, 0.0);
+      m[r * (size_t)S.nops + ref.idx] += c;
+    }
+  GemmBatch batch;
+  std::vector<int> cbufs;
+  GemmJob job;
+  job.C = BufRef{T.buf, 0};
+  job.m = T.nops;
+  job.n = (int)size;
+  job.ldc = size;
+  job.accumulate = 0;
+  job.tbeg = 0;
+  for (auto& [f, m] : coef) {
+    const Family& S = blk.family(f);
+    int cb = C.new_buf((int64_t)m.size());
+    C.ex->upload(C.ptr(cb), m.data(), m.size() * 8);
+    cbufs.push_back(cb);
+    GemmTerm gt;
+    gt.A = BufRef{cb, 0};
+    gt.lda = S.nops;
+    gt.B = BufRef{S.buf, 0};
+    gt.ldb = size;
+    gt.k = S.nops;
+    batch.terms.push_back(gt);
+  }
+  job.tend = (int64_t)batch.terms.size();
+  batch.jobs.push_back(job);
+  C.run_batch(batch);
+  for (int cb : cbufs) C.free_buf(cb);
+}
+
+void Context::to_complementary(Block& R) {
+  if (R.left || !R.normal) return;
+  const int b = R.b;
+  std::vector<std::pair<int, int>> ksym, kasym, kall;
+  for (int i = 0; i < b; ++i)
+    for (int j = 0; j < b; ++j) {
+      kall.push_back({i, j});
+      if (i <= j) ksym.push_back({i, j});
+      if (i < j) kasym.push_back({i, j});
+    }
+  xterms::StoredRightProv Y{R, &I};
+  auto build = [&](int f, const std::vector<std::pair<int, int>>& keys, auto expr) {
+    add_family(*this, R, f, keys);
+    std::vector<std::vector<std::pair<Ref, double>>> rows;
+    for (auto& [i, j] : keys) {
+      std::vector<std::pair<Ref, double>> row;
+      for (auto& [c, r] : expr(i, j)) row.push_back({r, c});
+      rows.push_back(row);
+    }
+    lincomb_into_family(*this, R, f, rows);
+  };
+  build(F_P0, ksym, [&](int i, int j) { return Y.Pn(0, i, j); });
+  build(F_P1, kasym, [&](int i, int j) { return Y.Pn(1, i, j); });
+  build(F_J, ksym, [&](int i, int j) { return Y.Jn(i, j); });
+  build(F_K0, kall, [&](int i, int j) { return Y.Kn(0, i, j); });
+  build(F_K1, kall, [&](int i, int j) { return Y.Kn(1, i, j); });
+  for (int f : {F_A0, F_A1, F_AB0, F_AB1, F_B0, F_B1}) {
+    free_buf(R.fam[f].buf);
+    R.fam[f] = Family{};
+  }
+  R.normal = false;
 }
 
 // ================================================================ batches
@@ -742,6 +863,9 @@ std::unique_ptr<Block> Context::grow_right(Block& R, const SiteTensor& B, const 
   N->left = false;
   N->b = R.b - 1;
   N->n = n;
+  // normal pairs while the right block is the smaller side of the chain
+  N->normal = R.normal && (n - N->b) <= N->b;
+  if (R.normal && !N->normal) to_complementary(R);
   N->bond = nb;
   init_families(*this, *N);
   const int o = R.b - 1;

@@ -93,6 +93,12 @@ class Context;
 
 struct Block {
   bool left = true;
+  // Right blocks only: true while the block stores normal pair operators
+  // (A, Abar, B for pairs inside it, like a left block) instead of the
+  // complementary P, J, K for pairs to its left.  Normal pairs are cheaper
+  // while the block is the smaller side of the chain; to_complementary()
+  // converts before the block meets a left block in H*psi.
+  bool normal = false;
   int b = 0, n = 0;
   Bond bond;
   std::map<std::pair<int, int>, std::unique_ptr<OpLayout>> layouts;
@@ -219,6 +225,7 @@ class Context {
   std::unique_ptr<Block> vacuum_right();
   std::unique_ptr<Block> grow_left(Block& L, const SiteTensor& A, const Bond& newbond);
   std::unique_ptr<Block> grow_right(Block& R, const SiteTensor& B, const Bond& newbond);
+  void to_complementary(Block& R);  // right block: normal pairs -> P, J, K over pairs to its left
   void free_block(Block& blk);
 
   // operator expressions
