@@ -71,6 +71,9 @@ typedef struct {
   int davidson_max_subspace;   /* basis size before restart                          */
   int hpsi_prec;               /* dmrg_prec used for the bulk matvecs in Davidson    */
   long long work_budget_elems; /* cap on intermediate buffers (elements), 0: default */
+  int keep_blocks;             /* 1: keep the operator blocks of every bond that
+                                  dmrg_set_mps builds, so dmrg_truncate can move
+                                  the two-site block (memory grows with n)        */
 } dmrg_opts;
 
 /* Create a context; copies h (n*n) and g (n^4).  Errors: ARG, SYMMETRY
@@ -112,14 +115,28 @@ int dmrg_heff_diag(dmrg_ctx *c, int k, double *diag);
 int dmrg_davidson_step(dmrg_ctx *c, int k, double *psi_inout, double *energy, double *resid_norm,
                        int *n_matvec_lowprec, int *n_matvec_fp64);
 
-/* Truncate psi at the middle cut to at most d_max multiplets (eps_tr > 0
- * additionally drops the smallest weights while their sum stays below eps_tr),
- * absorb the left part into a new left-canonical tensor A at site k, and grow
- * the left operator block to bond k+1 (direction +1).  trunc_err receives the
- * discarded weight, d_kept the kept multiplet count.  The singular values of
- * the cut (kept ones, descending per sector) can be read with dmrg_cut_spectrum. */
+/* Truncate psi at the middle cut (Sec. "Numerical procedure": fixed D, or a
+ * truncation-error threshold).  Multiplet weights are the eigenvalues of the
+ * reduced density matrix of the enlarged left block (direction +1) or the
+ * enlarged right block (direction -1), rho_a = sum_c psi_ac psi_ac^T, summed
+ * over spin projections; the d_max largest are kept (ties broken by 2S, N,
+ * index); eps_tr > 0 keeps fewer when the discarded weight stays <= eps_tr.
+ * The kept eigenvectors form a new left-canonical tensor at site k (+1) or a
+ * right-canonical tensor at site k+1 (-1), and the operator block is grown to
+ * bond k+1 on the GPU.  If keep_blocks was set, the two-site block then moves
+ * to (k+1, k+2) or (k-1, k).  trunc_err = discarded weight / total weight. */
 int dmrg_truncate(dmrg_ctx *c, int k, const double *psi, int direction, int d_max, double eps_tr,
                   double *trunc_err, int *d_kept);
+
+/* Read back bond b's sectors ((N, 2S, dim) rows, *n sectors) and site j's
+ * tensor (blocks in the canonical order of dmrg_set_mps, *n values); with a
+ * NULL output only the count is returned. */
+int dmrg_get_bond(dmrg_ctx *c, int b, int *sectors, int *n);
+int dmrg_get_site(dmrg_ctx *c, int j, double *values, long long *n);
+
+/* Left site index k of the current two-site block (-1 if the block could not
+ * move after a truncation because the needed operator block was not kept). */
+int dmrg_current_block(dmrg_ctx *c, int *k);
 
 /* Reduced singular values of the last truncation (all sectors, descending),
  * with their sector spins 2S; returns the count in *n. */

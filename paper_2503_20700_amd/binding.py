@@ -31,7 +31,7 @@ class Opts(ct.Structure):
     _fields_ = [("n_orb", ct.c_int), ("n_elec", ct.c_int), ("two_s", ct.c_int), ("e_core", ct.c_double),
                 ("davidson_tol", ct.c_double), ("davidson_max_iter", ct.c_int),
                 ("davidson_max_subspace", ct.c_int), ("hpsi_prec", ct.c_int),
-                ("work_budget_elems", ct.c_longlong)]
+                ("work_budget_elems", ct.c_longlong), ("keep_blocks", ct.c_int)]
 
 
 _LIBS = {}
@@ -61,6 +61,9 @@ def load(path=None):
         "dmrg_stats": (I, [P, dp, I]),
         "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
         "dmrg_kernel_timing": (I, [P, I, dp, llp]),
+        "dmrg_current_block": (I, [P, ip]),
+        "dmrg_get_bond": (I, [P, I, ip, ip]),
+        "dmrg_get_site": (I, [P, I, dp, llp]),
         "dmrg_last_error": (ct.c_char_p, []),
         "dmrg_destroy": (V, [P]),
     }
@@ -75,7 +78,8 @@ def load(path=None):
 def exported_symbols():
     return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_heff_diag",
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
-            "dmrg_kernel_timing", "dmrg_last_error", "dmrg_destroy"]
+            "dmrg_kernel_timing", "dmrg_current_block", "dmrg_get_bond", "dmrg_get_site", "dmrg_last_error",
+            "dmrg_destroy"]
 
 
 def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ident_b=False, alpha=1.0, beta=0.0,
@@ -111,13 +115,13 @@ class DMRG:
     """One context: integrals, an MPS around a two-site block, and its H*psi."""
 
     def __init__(self, h, g, n_elec, two_s, e_core=0.0, davidson_tol=1e-7, davidson_max_iter=60,
-                 davidson_max_subspace=16, hpsi_prec=FP64, work_budget_elems=0, lib=None):
+                 davidson_max_subspace=24, hpsi_prec=FP64, work_budget_elems=0, keep_blocks=False, lib=None):
         self.lib = load(lib)
         h = np.ascontiguousarray(h, dtype=np.float64)
         g = np.ascontiguousarray(g, dtype=np.float64)
         n = h.shape[0]
         self.opts = Opts(n, n_elec, two_s, e_core, davidson_tol, davidson_max_iter, davidson_max_subspace,
-                         hpsi_prec, work_budget_elems)
+                         hpsi_prec, work_budget_elems, int(keep_blocks))
         self._h = ct.c_void_p()
         self._check(self.lib.dmrg_create(ct.byref(self._h), ct.byref(self.opts), _dp(h), _dp(g)))
         self.k = None
@@ -184,7 +188,24 @@ class DMRG:
         err, kept = ct.c_double(), ct.c_int()
         self._check(self.lib.dmrg_truncate(self._h, self.k, _dp(psi), direction, d_max, eps_tr, ct.byref(err),
                                            ct.byref(kept)))
+        kk = ct.c_int()
+        self._check(self.lib.dmrg_current_block(self._h, ct.byref(kk)))
+        self.k = kk.value
         return err.value, kept.value
+
+    def get_bond(self, b):
+        n = ct.c_int()
+        self._check(self.lib.dmrg_get_bond(self._h, b, None, ct.byref(n)))
+        out = np.zeros(3 * max(n.value, 1), dtype=np.int32)
+        self._check(self.lib.dmrg_get_bond(self._h, b, out.ctypes.data_as(ct.POINTER(ct.c_int)), ct.byref(n)))
+        return [tuple(int(x) for x in out[3 * i:3 * i + 3]) for i in range(n.value)]
+
+    def get_site(self, j):
+        n = ct.c_longlong()
+        self._check(self.lib.dmrg_get_site(self._h, j, None, ct.byref(n)))
+        out = np.zeros(max(n.value, 1))
+        self._check(self.lib.dmrg_get_site(self._h, j, _dp(out), ct.byref(n)))
+        return out[:n.value]
 
     def cut_spectrum(self, capacity=1 << 20):
         vals = np.zeros(capacity)

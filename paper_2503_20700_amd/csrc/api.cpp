@@ -33,6 +33,8 @@ bool finite_all(const double* p, size_t n) {
 
 extern "C" const char* dmrg_last_error(void) { return g_err.c_str(); }
 
+int dmrg_fail(int code, const std::string& msg) { return fail(code, msg); }
+
 extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, const double* g) {
   if (!out || !o || !h || !g) return fail(DMRG_ERR_ARG, "dmrg_create: null argument");
   *out = nullptr;
@@ -142,17 +144,28 @@ extern "C" int dmrg_set_mps(dmrg_ctx* c, int k, const int* bs, const int* counts
       std::fprintf(stderr, "[dmrg] %s block at bond %d: %.2f GB, %.1f s\n", side, b, blk.bytes_f64() / 1e9, s);
       std::fflush(stderr);
     };
+    const bool keep = c->opts.keep_blocks != 0;
+    for (auto& h : C.Lhist)
+      if (h) C.free_block(*h);
+    for (auto& h : C.Rhist)
+      if (h) C.free_block(*h);
+    C.Lhist.clear();
+    C.Rhist.clear();
+    C.Lhist.resize(n + 1);
+    C.Rhist.resize(n + 1);
     auto L = C.vacuum_left();
     for (int j = 0; j < k; ++j) {
       auto N = C.grow_left(*L, C.sites[j], C.bonds[j + 1]);
-      C.free_block(*L);
+      if (keep) C.Lhist[j] = std::move(L);
+      else C.free_block(*L);
       L = std::move(N);
       progress("left", j + 1, *L);
     }
     auto R = C.vacuum_right();
     for (int j = n - 1; j >= k + 2; --j) {
       auto N = C.grow_right(*R, C.sites[j], C.bonds[j]);
-      C.free_block(*R);
+      if (keep) C.Rhist[j + 1] = std::move(R);
+      else C.free_block(*R);
       R = std::move(N);
       progress("right", j, *R);
     }

@@ -1,9 +1,582 @@
-// Davidson eigensolver and truncation at the two-site block.
+// Davidson eigensolver at the two-site block (lowest state of H_eff).
+//
+// The residual criterion ||H x - theta x||_2 <= tol for ||x|| = 1 is the
+// paper's (Sec. "Numerical procedure", residual 1e-7).  With a low-precision
+// bulk matvec (FP32 or BF16 operands, FP32 accumulation) the iteration runs
+// in two phases: (1) Davidson with low-precision matvecs until the residual
+// reaches the precision's noise floor, (2) FP64 refinement: Davidson
+// restarted from the phase-1 Ritz vector with FP64 matvecs until tol.  All
+// vectors, projections (dot products), orthogonalisation and residuals are
+// FP64 on the GPU; only the small projected matrix (<= 32 x 32) is
+// diagonalised on the host.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <random>
+#include <tuple>
 #include <string>
+#include <vector>
 
 #include "../../include/dmrg.h"
 #include "session.hpp"
 
-extern "C" int dmrg_davidson_step(dmrg_ctx*, int, double*, double*, double*, int*, int*) { return DMRG_ERR_ARG; }
-extern "C" int dmrg_truncate(dmrg_ctx*, int, const double*, int, int, double, double*, int*) { return DMRG_ERR_ARG; }
-extern "C" int dmrg_cut_spectrum(dmrg_ctx*, double*, int*, int*, int) { return DMRG_ERR_ARG; }
+using namespace dmrg;
+
+namespace {
+
+
+// Cyclic Jacobi for a small symmetric matrix (row-major m x m); returns
+// eigenvalues ascending and eigenvectors as columns of V.
+void jacobi_eig(int m, std::vector<double> A, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) V[(size_t)i * m + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) off += A[(size_t)p * m + q] * A[(size_t)p * m + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = A[(size_t)p * m + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = A[(size_t)p * m + p], aqq = A[(size_t)q * m + q];
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < m; ++k) {
+          const double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
+          A[(size_t)k * m + p] = c * akp - s * akq;
+          A[(size_t)k * m + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
+          A[(size_t)p * m + k] = c * apk - s * aqk;
+          A[(size_t)q * m + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double vkp = V[(size_t)k * m + p], vkq = V[(size_t)k * m + q];
+          V[(size_t)k * m + p] = c * vkp - s * vkq;
+          V[(size_t)k * m + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  std::vector<int> order(m);
+  for (int i = 0; i < m; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return A[(size_t)a * m + a] < A[(size_t)b * m + b]; });
+  w.resize(m);
+  std::vector<double> Vs((size_t)m * m);
+  for (int j = 0; j < m; ++j) {
+    w[j] = A[(size_t)order[j] * m + order[j]];
+    for (int i = 0; i < m; ++i) Vs[(size_t)i * m + j] = V[(size_t)i * m + order[j]];
+  }
+  V.swap(Vs);
+}
+
+struct Workspace {
+  int bV = -1, bW = -1, bx = -1, bhx = -1, br = -1, bt = -1;
+  int64_t n = 0;
+  int mmax = 0;
+};
+
+constexpr int kKeep = 4;  // Ritz vectors kept at a restart
+
+double* P(dmrg_ctx* c, int b) { return (double*)c->C->ptr(b); }
+
+// y = H x for device FP64 vectors via the plan buffers.
+void matvec(dmrg_ctx* c, const double* x, double* y, int prec, int64_t n) {
+  c->ex->copy_d2d(c->C->ptr(c->b_in), x, (size_t)n * 8);
+  c->hpsi_device(prec);
+  c->ex->copy_d2d(y, c->C->ptr(c->b_out), (size_t)n * 8);
+}
+
+struct PhaseResult {
+  double theta = 0.0, resid = 0.0;
+  int matvecs = 0;
+  bool converged = false;
+};
+
+// Davidson on the device basis V (rows), W = H V; starts from x (normalised).
+PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int max_iter) {
+  Executor* ex = c->ex.get();
+  const int64_t n = ws.n;
+  const int mmax = ws.mmax;
+  double* V = P(c, ws.bV);
+  double* W = P(c, ws.bW);
+  double* x = P(c, ws.bx);
+  double* hx = P(c, ws.bhx);
+  double* r = P(c, ws.br);
+  double* t = P(c, ws.bt);
+  const double* diag = (const double*)c->C->ptr(c->b_diag);
+  PhaseResult res;
+  std::vector<double> G((size_t)mmax * mmax, 0.0), tmp(mmax), w, Y;
+  // V_0 = x, W_0 = H x
+  ex->copy_d2d(V, x, (size_t)n * 8);
+  matvec(c, V, W, prec, n);
+  res.matvecs++;
+  int m = 1;
+  ex->multidot(W, n, 1, V, n, tmp.data());
+  G[0] = tmp[0];
+  for (int it = 0; it < max_iter; ++it) {
+    // Rayleigh-Ritz on span(V)
+    std::vector<double> Gm((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Gm[(size_t)i * m + j] = 0.5 * (G[(size_t)i * mmax + j] + G[(size_t)j * mmax + i]);
+    jacobi_eig(m, Gm, w, Y);
+    const double theta = w[0];
+    std::vector<double> y0(m);
+    for (int i = 0; i < m; ++i) y0[i] = Y[(size_t)i * m + 0];
+    ex->combine(x, V, n, m, y0.data(), n, 0.0);
+    ex->combine(hx, W, n, m, y0.data(), n, 0.0);
+    ex->axpby(r, 1.0, hx, -theta, x, n);
+    double rr = 0.0;
+    ex->multidot(r, n, 1, r, n, &rr);
+    res.theta = theta;
+    res.resid = std::sqrt(std::max(rr, 0.0));
+    if (std::getenv("DMRG_VERBOSE"))
+      std::fprintf(stderr, "[davidson] prec %d it %d m %d theta %.12f resid %.3e\n", prec, it, m, theta, res.resid);
+    if (res.resid <= tol) {
+      res.converged = true;
+      break;
+    }
+    if (it == max_iter - 1) break;
+    // thick restart: rotate the basis onto the `keep` lowest Ritz vectors,
+    // built in the spare rows mmax..mmax+keep-1 and then moved to the front.
+    if (m == mmax) {
+      const int keep = kKeep;
+      for (int q = 0; q < keep; ++q) {
+        std::vector<double> yq(m);
+        for (int i = 0; i < m; ++i) yq[i] = Y[(size_t)i * m + q];
+        ex->combine(V + (int64_t)(mmax + q) * n, V, n, m, yq.data(), n, 0.0);
+        ex->combine(W + (int64_t)(mmax + q) * n, W, n, m, yq.data(), n, 0.0);
+      }
+      for (int q = 0; q < keep; ++q) {
+        ex->copy_d2d(V + (int64_t)q * n, V + (int64_t)(mmax + q) * n, (size_t)n * 8);
+        ex->copy_d2d(W + (int64_t)q * n, W + (int64_t)(mmax + q) * n, (size_t)n * 8);
+      }
+      std::fill(G.begin(), G.end(), 0.0);
+      for (int q = 0; q < keep; ++q) G[(size_t)q * mmax + q] = w[q];
+      m = keep;
+      ex->axpby(r, 1.0, hx, -theta, x, n);
+    }
+    // correction t = (theta - D)^-1 r, orthogonalised against V twice
+    ex->precond(t, r, diag, theta, 1e-8, n);
+    for (int pass = 0; pass < 2; ++pass) {
+      ex->multidot(V, n, m, t, n, tmp.data());
+      for (int i = 0; i < m; ++i) tmp[i] = -tmp[i];
+      ex->combine(t, V, n, m, tmp.data(), n, 1.0);
+    }
+    double tt = 0.0;
+    ex->multidot(t, n, 1, t, n, &tt);
+    if (!(tt > 1e-28)) {
+      // preconditioned residual lies in the basis: fall back to the residual
+      ex->copy_d2d(t, r, (size_t)n * 8);
+      for (int pass = 0; pass < 2; ++pass) {
+        ex->multidot(V, n, m, t, n, tmp.data());
+        for (int i = 0; i < m; ++i) tmp[i] = -tmp[i];
+        ex->combine(t, V, n, m, tmp.data(), n, 1.0);
+      }
+      ex->multidot(t, n, 1, t, n, &tt);
+      if (!(tt > 1e-28)) break;
+    }
+    const double inv = 1.0 / std::sqrt(tt);
+    ex->axpby(V + (int64_t)m * n, inv, t, 0.0, t, n);
+    matvec(c, V + (int64_t)m * n, W + (int64_t)m * n, prec, n);
+    res.matvecs++;
+    // new row / column of the projected matrix
+    ex->multidot(W, n, m + 1, V + (int64_t)m * n, n, tmp.data());  // <W_j, V_m>
+    for (int j = 0; j <= m; ++j) G[(size_t)m * mmax + j] = tmp[j];
+    ex->multidot(V, n, m + 1, W + (int64_t)m * n, n, tmp.data());  // <V_j, W_m>
+    for (int j = 0; j <= m; ++j) G[(size_t)j * mmax + m] = tmp[j];
+    ++m;
+  }
+  return res;
+}
+
+// Davidson buffers owned by the context (freed with the H*psi plan).
+Workspace workspace(dmrg_ctx* c, int64_t n, int mmax) {
+  if (c->work_bufs.empty() || c->work_n != n || c->work_mmax != mmax) {
+    for (int b : c->work_bufs) c->C->free_buf(b);
+    c->work_bufs = {c->C->new_buf((int64_t)(mmax + kKeep) * n), c->C->new_buf((int64_t)(mmax + kKeep) * n), c->C->new_buf(n),
+                    c->C->new_buf(n), c->C->new_buf(n), c->C->new_buf(n)};
+    c->work_n = n;
+    c->work_mmax = mmax;
+  }
+  Workspace ws;
+  ws.n = n;
+  ws.mmax = mmax;
+  ws.bV = c->work_bufs[0];
+  ws.bW = c->work_bufs[1];
+  ws.bx = c->work_bufs[2];
+  ws.bhx = c->work_bufs[3];
+  ws.br = c->work_bufs[4];
+  ws.bt = c->work_bufs[5];
+  return ws;
+}
+}  // namespace
+
+extern "C" int dmrg_davidson_step(dmrg_ctx* c, int k, double* psi, double* energy, double* resid, int* nlo, int* nhi) {
+  if (!c || !psi || !energy || !resid) return dmrg_fail(DMRG_ERR_ARG, "dmrg_davidson_step: null argument");
+  if (!c->C->Lblk || k != c->C->k) return dmrg_fail(DMRG_ERR_ARG, "dmrg_davidson_step: no MPS loaded at this k");
+  try {
+    c->ensure_plan();
+    const int64_t n = c->plan->lay.size;
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(psi[i])) return dmrg_fail(DMRG_ERR_NONFINITE, "dmrg_davidson_step: non-finite start vector");
+    const int mmax = std::max(8, std::min(48, c->opts.davidson_max_subspace > 0 ? c->opts.davidson_max_subspace : 24));
+    const int max_iter = c->opts.davidson_max_iter > 0 ? c->opts.davidson_max_iter : 60;
+    const double tol = c->opts.davidson_tol > 0 ? c->opts.davidson_tol : 1e-7;
+    Workspace ws = workspace(c, n, mmax);
+    // start vector
+    std::vector<double> h0(psi, psi + n);
+    double nrm = 0.0;
+    for (double v : h0) nrm += v * v;
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+      std::mt19937_64 rng(12345);
+      std::normal_distribution<double> nd;
+      nrm = 0.0;
+      for (auto& v : h0) {
+        v = nd(rng);
+        nrm += v * v;
+      }
+    }
+    const double s = 1.0 / std::sqrt(nrm);
+    for (auto& v : h0) v *= s;
+    c->ex->upload(c->C->ptr(ws.bx), h0.data(), (size_t)n * 8);
+    const int prec = c->opts.hpsi_prec;
+    int lo = 0, hi = 0;
+    PhaseResult pr;
+    if (prec != DMRG_FP64) {
+      // phase 1: low-precision matvecs down to the precision's noise floor
+      const double floor_tol = (prec == DMRG_BF16) ? 3e-3 : 1e-5;
+      pr = davidson_phase(c, ws, prec, std::max(tol, floor_tol), max_iter);
+      lo = pr.matvecs;
+    }
+    // phase 2 (or the whole solve for FP64): FP64 matvecs to tol
+    pr = davidson_phase(c, ws, DMRG_FP64, tol, max_iter);
+    hi = pr.matvecs;
+    c->ex->download(psi, c->C->ptr(ws.bx), (size_t)n * 8);
+    *energy = pr.theta + c->opts.e_core;
+    *resid = pr.resid;
+    if (nlo) *nlo = lo;
+    if (nhi) *nhi = hi;
+    if (!pr.converged) return dmrg_fail(DMRG_ERR_NOCONV, "dmrg_davidson_step: residual above tolerance");
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_davidson_step: ") + e.what());
+  }
+}
+
+namespace {
+struct CutSector {
+  int n = 0, s2 = 0;           // quantum numbers of the enlarged block on the cut side
+  int dim = 0;                 // rows (direction +1) or columns (-1) of its super-blocks
+  std::vector<int> sbs;        // super-blocks with this sector on the cut side
+  int64_t off = 0;             // offset of its rho / eigenvector matrices
+};
+}  // namespace
+
+extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int d_max, double eps_tr,
+                             double* trunc_err, int* d_kept) {
+  if (!c || !psi || !trunc_err || !d_kept) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: null argument");
+  if (dir != 1 && dir != -1) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: direction must be +1 or -1");
+  if (d_max < 1 || !(eps_tr >= 0.0)) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: bad d_max / eps_tr");
+  if (!c->C->Lblk || k != c->C->k) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: no MPS loaded at this k");
+  Context& C = *c->C;
+  Executor* ex = c->ex.get();
+  try {
+    c->ensure_plan();
+    const PsiLayout lay = c->plan->lay;  // copy: the plan is reset below
+    const int64_t n = lay.size;
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(psi[i])) return dmrg_fail(DMRG_ERR_NONFINITE, "dmrg_truncate: non-finite psi");
+    ex->upload(C.ptr(c->b_in), psi, (size_t)n * 8);
+    // ---- sectors of the cut side
+    std::vector<CutSector> secs;
+    std::map<std::pair<int, int>, int> sec_of;
+    for (size_t s = 0; s < lay.sbs.size(); ++s) {
+      const auto& sb = lay.sbs[s];
+      const std::pair<int, int> key = dir > 0 ? std::make_pair(sb.an, sb.as2) : std::make_pair(sb.cn, sb.cs2);
+      auto it = sec_of.find(key);
+      if (it == sec_of.end()) {
+        CutSector cs;
+        cs.n = key.first;
+        cs.s2 = key.second;
+        cs.dim = dir > 0 ? sb.nrows : sb.ncols;
+        sec_of[key] = (int)secs.size();
+        secs.push_back(cs);
+        it = sec_of.find(key);
+      }
+      secs[it->second].sbs.push_back((int)s);
+    }
+    std::sort(secs.begin(), secs.end(), [](const CutSector& a, const CutSector& b) {
+      return a.n != b.n ? a.n < b.n : a.s2 < b.s2;
+    });
+    int64_t tot = 0;
+    std::vector<int64_t> offs;
+    std::vector<int> sizes;
+    for (auto& s : secs) {
+      s.off = tot;
+      offs.push_back(tot);
+      sizes.push_back(s.dim);
+      tot += (int64_t)s.dim * s.dim;
+    }
+    // ---- reduced density matrices rho = sum psi psi^T (or psi^T psi) on the GPU
+    const int bR = C.new_buf(std::max<int64_t>(tot, 1)), bV = C.new_buf(std::max<int64_t>(tot, 1));
+    GemmBatch gb;
+    for (auto& s : secs) {
+      GemmJob j;
+      j.C = BufRef{bR, s.off};
+      j.m = s.dim;
+      j.n = s.dim;
+      j.ldc = s.dim;
+      j.tbeg = (int64_t)gb.terms.size();
+      for (int sbi : s.sbs) {
+        const auto& sb = lay.sbs[sbi];
+        GemmTerm t;
+        t.A = BufRef{-PH_IN, sb.off};
+        t.B = BufRef{-PH_IN, sb.off};
+        t.lda = sb.ncols;
+        t.ldb = sb.ncols;
+        if (dir > 0) {
+          t.flags = TF_TRANS_B;
+          t.k = sb.ncols;
+        } else {
+          t.flags = TF_TRANS_A;
+          t.k = sb.nrows;
+        }
+        gb.terms.push_back(t);
+      }
+      j.tend = (int64_t)gb.terms.size();
+      gb.jobs.push_back(j);
+    }
+    c->bind();
+    C.run_batch(gb);
+    ex->sym_eig((double*)C.ptr(bR), (double*)C.ptr(bV), offs, sizes, 40, 1e-15);
+    std::vector<double> hR((size_t)tot), hV((size_t)tot);
+    ex->download(hR.data(), C.ptr(bR), (size_t)tot * 8);
+    ex->download(hV.data(), C.ptr(bV), (size_t)tot * 8);
+    C.free_buf(bR);
+    C.free_buf(bV);
+    // ---- select kept multiplets
+    struct W {
+      double w;
+      int s2, n, sec, idx;
+    };
+    std::vector<W> all;
+    double wsum = 0.0;
+    for (size_t si = 0; si < secs.size(); ++si)
+      for (int i = 0; i < secs[si].dim; ++i) {
+        double w = std::max(0.0, hR[(size_t)secs[si].off + (size_t)i * secs[si].dim + i]);
+        all.push_back(W{w, secs[si].s2, secs[si].n, (int)si, i});
+        wsum += w;
+      }
+    if (!(wsum > 0.0)) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: zero wavefunction");
+    std::sort(all.begin(), all.end(), [](const W& a, const W& b) {
+      if (a.w != b.w) return a.w > b.w;
+      if (a.s2 != b.s2) return a.s2 < b.s2;
+      if (a.n != b.n) return a.n < b.n;
+      return a.sec != b.sec ? a.sec < b.sec : a.idx < b.idx;
+    });
+    size_t keepn = std::min<size_t>((size_t)d_max, all.size());
+    if (eps_tr > 0.0) {  // fewest multiplets whose discarded weight stays <= eps_tr
+      double disc = 0.0;
+      size_t m = all.size();
+      while (m > 1 && disc + all[m - 1].w <= eps_tr * wsum) {
+        disc += all[m - 1].w;
+        --m;
+      }
+      keepn = std::min(keepn, m);
+    }
+    double kept_w = 0.0;
+    std::vector<std::vector<int>> kept(secs.size());
+    c->cut_values.clear();
+    c->cut_spins.clear();
+    for (size_t i = 0; i < keepn; ++i) {
+      kept[all[i].sec].push_back(all[i].idx);
+      kept_w += all[i].w;
+      c->cut_values.push_back(std::sqrt(all[i].w / wsum));
+      c->cut_spins.push_back(all[i].s2);
+    }
+    *trunc_err = std::max(0.0, 1.0 - kept_w / wsum);
+    *d_kept = (int)keepn;
+    // ---- new bond and site tensor (kept eigenvectors, descending weight per sector)
+    Bond nb;
+    std::vector<int> new_of(secs.size(), -1);
+    for (size_t si = 0; si < secs.size(); ++si) {
+      if (kept[si].empty()) continue;
+      new_of[si] = (int)nb.secs.size();
+      nb.secs.push_back(Sector{secs[si].n, secs[si].s2, (int)kept[si].size()});
+    }
+    SiteTensor T;
+    T.left = dir > 0;
+    T.j = dir > 0 ? k : k + 1;
+    const Bond& lb = C.Lblk->bond;
+    const Bond& rb = C.Rblk->bond;
+    std::vector<double> vals;
+    // Left: blocks (l, sigma1, a) in (l, sigma, a) order; rows of a are the (l, sigma1) sub-blocks.
+    // Right: blocks (c, sigma2, r) in (c, sigma, r) order; columns of c are the (sigma2, r) sub-blocks.
+    auto sub_of = [&](const CutSector& s, int first, int sig, int& off, int& dim) {
+      const auto& sb = lay.sbs[s.sbs[0]];
+      if (dir > 0) {
+        for (auto& r : sb.rows)
+          if (r.il == first && r.s1 == sig) {
+            off = r.r0;
+            dim = r.dl;
+            return true;
+          }
+      } else {
+        for (auto& cl : sb.cols)
+          if (cl.ir == first && cl.s2 == sig) {
+            off = cl.c0;
+            dim = cl.dr;
+            return true;
+          }
+      }
+      return false;
+    };
+    const Bond& outer = dir > 0 ? lb : rb;  // the bond on the far side of the site
+    int64_t voff = 0;
+    if (dir > 0) {
+      for (size_t il = 0; il < outer.secs.size(); ++il)
+        for (int sig = 0; sig < 3; ++sig)
+          for (size_t si = 0; si < secs.size(); ++si) {
+            if (new_of[si] < 0) continue;
+            int off, dim;
+            if (!sub_of(secs[si], (int)il, sig, off, dim)) continue;
+            const int da = (int)kept[si].size();
+            T.find[{(int)il, sig, new_of[si]}] = (int)T.blocks.size();
+            T.blocks.push_back(SiteTensor::Blk{(int)il, sig, new_of[si], voff, dim, da});
+            for (int r = 0; r < dim; ++r)
+              for (int q = 0; q < da; ++q)
+                vals.push_back(hV[(size_t)secs[si].off + (size_t)(off + r) * secs[si].dim + kept[si][q]]);
+            voff += (int64_t)dim * da;
+          }
+    } else {
+      for (size_t si = 0; si < secs.size(); ++si) {
+        if (new_of[si] < 0) continue;
+        for (int sig = 0; sig < 3; ++sig)
+          for (size_t ir = 0; ir < outer.secs.size(); ++ir) {
+            int off, dim;
+            if (!sub_of(secs[si], (int)ir, sig, off, dim)) continue;
+            const int dc = (int)kept[si].size();
+            T.find[{new_of[si], sig, (int)ir}] = (int)T.blocks.size();
+            T.blocks.push_back(SiteTensor::Blk{new_of[si], sig, (int)ir, voff, dc, dim});
+            for (int q = 0; q < dc; ++q)
+              for (int r = 0; r < dim; ++r)
+                vals.push_back(hV[(size_t)secs[si].off + (size_t)(off + r) * secs[si].dim + kept[si][q]]);
+            voff += (int64_t)dc * dim;
+          }
+      }
+      // canonical (c, sigma, r) order
+      std::vector<size_t> ord(T.blocks.size());
+      for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+      std::sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+        const auto &x = T.blocks[a], &y = T.blocks[b];
+        return std::tie(x.s0, x.sig, x.s1) < std::tie(y.s0, y.sig, y.s1);
+      });
+      std::vector<SiteTensor::Blk> nbk;
+      std::vector<double> nv;
+      T.find.clear();
+      for (size_t i : ord) {
+        auto bk = T.blocks[i];
+        const size_t cnt = (size_t)bk.rows * bk.cols;
+        std::vector<double> tmp(vals.begin() + bk.off, vals.begin() + bk.off + cnt);
+        bk.off = (int64_t)nv.size();
+        nv.insert(nv.end(), tmp.begin(), tmp.end());
+        T.find[{bk.s0, bk.sig, bk.s1}] = (int)nbk.size();
+        nbk.push_back(bk);
+      }
+      T.blocks.swap(nbk);
+      vals.swap(nv);
+    }
+    T.buf = C.new_buf(std::max<int64_t>((int64_t)vals.size(), 1));
+    if (!vals.empty()) ex->upload(C.ptr(T.buf), vals.data(), vals.size() * 8);
+    // ---- grow the operator block across the cut, move the two-site block if possible
+    c->reset_plan();
+    const bool keep = c->opts.keep_blocks != 0;
+    if (dir > 0) {
+      auto N = C.grow_left(*C.Lblk, T, nb);
+      if (keep) C.Lhist[k] = std::move(C.Lblk);
+      else C.free_block(*C.Lblk);
+      C.Lblk = std::move(N);
+      C.free_buf(C.sites[k].buf);
+      C.sites[k] = T;
+      C.bonds[k + 1] = nb;
+      if (k + 3 <= C.n && C.Rhist.size() > (size_t)(k + 3) && C.Rhist[k + 3]) {
+        C.Rhist[k + 2] = std::move(C.Rblk);
+        C.Rblk = std::move(C.Rhist[k + 3]);
+        C.k = k + 1;
+      } else {
+        C.k = -1;
+      }
+    } else {
+      auto N = C.grow_right(*C.Rblk, T, nb);
+      if (keep) C.Rhist[k + 2] = std::move(C.Rblk);
+      else C.free_block(*C.Rblk);
+      C.Rblk = std::move(N);
+      C.free_buf(C.sites[k + 1].buf);
+      C.sites[k + 1] = T;
+      C.bonds[k + 1] = nb;
+      if (k - 1 >= 0 && C.Lhist.size() > (size_t)(k - 1) && C.Lhist[k - 1]) {
+        C.Lhist[k] = std::move(C.Lblk);
+        C.Lblk = std::move(C.Lhist[k - 1]);
+        C.k = k - 1;
+      } else {
+        C.k = -1;
+      }
+    }
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_truncate: ") + e.what());
+  }
+}
+
+extern "C" int dmrg_cut_spectrum(dmrg_ctx* c, double* values, int* two_s, int* n, int capacity) {
+  if (!c || !n) return dmrg_fail(DMRG_ERR_ARG, "dmrg_cut_spectrum: null argument");
+  const int cnt = (int)c->cut_values.size();
+  *n = cnt;
+  for (int i = 0; i < cnt && i < capacity; ++i) {
+    if (values) values[i] = c->cut_values[i];
+    if (two_s) two_s[i] = c->cut_spins[i];
+  }
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_get_bond(dmrg_ctx* c, int b, int* sectors, int* n) {
+  if (!c || !n) return dmrg_fail(DMRG_ERR_ARG, "dmrg_get_bond: null argument");
+  if (b < 0 || b >= (int)c->C->bonds.size()) return dmrg_fail(DMRG_ERR_ARG, "dmrg_get_bond: bond out of range");
+  const Bond& bd = c->C->bonds[b];
+  *n = (int)bd.secs.size();
+  if (sectors)
+    for (size_t i = 0; i < bd.secs.size(); ++i) {
+      sectors[3 * i] = bd.secs[i].n;
+      sectors[3 * i + 1] = bd.secs[i].s2;
+      sectors[3 * i + 2] = bd.secs[i].dim;
+    }
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_get_site(dmrg_ctx* c, int j, double* values, long long* n) {
+  if (!c || !n) return dmrg_fail(DMRG_ERR_ARG, "dmrg_get_site: null argument");
+  if (j < 0 || j >= (int)c->C->sites.size() || c->C->sites[j].buf < 0)
+    return dmrg_fail(DMRG_ERR_ARG, "dmrg_get_site: no tensor held for this site");
+  const SiteTensor& T = c->C->sites[j];
+  int64_t cnt = 0;
+  for (auto& b : T.blocks) cnt += (int64_t)b.rows * b.cols;
+  *n = cnt;
+  try {
+    if (values && cnt) c->ex->download(values, c->C->ptr(T.buf), (size_t)cnt * 8);
+  } catch (const std::exception& e) {
+    return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_get_site: ") + e.what());
+  }
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_current_block(dmrg_ctx* c, int* k) {
+  if (!c || !k) return dmrg_fail(DMRG_ERR_ARG, "dmrg_current_block: null argument");
+  *k = c->C->k;
+  return DMRG_OK;
+}

@@ -94,6 +94,13 @@ class Executor {
   virtual void axpby(double* z, double a, const double* x, double b, const double* y, int64_t n) = 0;
   // t_i = r_i / (theta - d_i), with |theta - d_i| floored at eps
   virtual void precond(double* t, const double* r, const double* d, double theta, double eps, int64_t n) = 0;
+  // Batched symmetric eigensolver (FP64): matrix i is sizes[i] x sizes[i],
+  // row-major at A + offs[i]; on return its diagonal holds the eigenvalues
+  // (unordered) and V + offs[i] the eigenvectors as columns.  Two-sided Jacobi
+  // with parallel (round-robin) ordering, one work-group per matrix; stops
+  // when the off-diagonal Frobenius norm falls below tol * ||A||_F.
+  virtual void sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes,
+                       int max_sweeps, double tol) = 0;
   // Per-launch timing of run() with device events on the executor's stream.
   // kernel_time() synchronises and returns (total ms, launches) since the
   // last call to timing(true).

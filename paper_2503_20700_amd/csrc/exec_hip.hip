@@ -295,6 +295,120 @@ __global__ void precond_kernel(double* t, const double* r, const double* d, doub
   }
 }
 
+// ---- batched parallel Jacobi eigensolver (one work-group per matrix)
+// Round-robin (circle) ordering over np = n rounded up to even "players":
+// in round r player 0 meets player (r % (np-1)) + 1 ... every round pairs are
+// disjoint, so all row rotations and then all column rotations of a round
+// compose to J^T A J with J the product of the round's plane rotations.
+__device__ __forceinline__ void rr_pair(int t, int r, int np, int& p, int& q) {
+  const int m = np - 1;
+  if (t == 0) {
+    p = np - 1;
+    q = r % m;
+  } else {
+    p = (r + t) % m;
+    q = (r - t + m) % m;
+  }
+  if (p > q) {
+    int x = p;
+    p = q;
+    q = x;
+  }
+}
+
+__global__ __launch_bounds__(256) void jacobi_kernel(double* __restrict__ Aall, double* __restrict__ Vall,
+                                                     const long long* __restrict__ offs, const int* __restrict__ sizes,
+                                                     int max_sweeps, double tol) {
+  const int n = sizes[blockIdx.x];
+  double* A = Aall + offs[blockIdx.x];
+  double* V = Vall + offs[blockIdx.x];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double red[256];
+  __shared__ double cs[512], sn[512];
+  __shared__ int pp[512], qq[512];
+  __shared__ double stop_flag;
+  for (long long i = tid; i < (long long)n * n; i += nt) V[i] = ((i / n) == (i % n)) ? 1.0 : 0.0;
+  if (n <= 1) return;
+  const int np = n + (n & 1);
+  const int npairs = np / 2;
+  __syncthreads();
+  // ||A||_F^2
+  double fs = 0.0;
+  for (long long i = tid; i < (long long)n * n; i += nt) fs += A[i] * A[i];
+  red[tid] = fs;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  const double fro2 = red[0];
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double off = 0.0;
+    for (long long i = tid; i < (long long)n * n; i += nt)
+      if ((i / n) != (i % n)) off += A[i] * A[i];
+    red[tid] = off;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) stop_flag = (red[0] <= tol * tol * fro2) ? 1.0 : 0.0;
+    __syncthreads();
+    if (stop_flag != 0.0) break;
+    for (int r = 0; r < np - 1; ++r) {
+      // rotation angles for this round (pairs processed in slices of 512)
+      for (int t0 = 0; t0 < npairs; t0 += 512) {
+        const int cnt = min(512, npairs - t0);
+        for (int t = tid; t < cnt; t += nt) {
+          int p, q;
+          rr_pair(t0 + t, r, np, p, q);
+          double c = 1.0, s = 0.0;
+          if (q < n) {
+            const double apq = A[(long long)p * n + q];
+            if (apq != 0.0) {
+              const double app = A[(long long)p * n + p], aqq = A[(long long)q * n + q];
+              const double tau = (aqq - app) / (2.0 * apq);
+              const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+              c = 1.0 / sqrt(1.0 + tt * tt);
+              s = tt * c;
+            }
+          }
+          cs[t] = c;
+          sn[t] = s;
+          pp[t] = p;
+          qq[t] = (q < n) ? q : -1;
+        }
+        __syncthreads();
+        // rows p, q of A
+        for (long long i = tid; i < (long long)cnt * n; i += nt) {
+          const int t = (int)(i / n), k = (int)(i % n);
+          if (qq[t] < 0 || sn[t] == 0.0) continue;
+          const long long ip = (long long)pp[t] * n + k, iq = (long long)qq[t] * n + k;
+          const double a = A[ip], b = A[iq];
+          A[ip] = cs[t] * a - sn[t] * b;
+          A[iq] = sn[t] * a + cs[t] * b;
+        }
+        __syncthreads();
+        // columns p, q of A and of V
+        for (long long i = tid; i < (long long)cnt * n; i += nt) {
+          const int t = (int)(i / n), k = (int)(i % n);
+          if (qq[t] < 0 || sn[t] == 0.0) continue;
+          const long long ip = (long long)k * n + pp[t], iq = (long long)k * n + qq[t];
+          double a = A[ip], b = A[iq];
+          A[ip] = cs[t] * a - sn[t] * b;
+          A[iq] = sn[t] * a + cs[t] * b;
+          a = V[ip];
+          b = V[iq];
+          V[ip] = cs[t] * a - sn[t] * b;
+          V[iq] = sn[t] * a + cs[t] * b;
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 struct Prepared {
   RawJob* d_jobs = nullptr;
   RawTerm* d_terms = nullptr;
@@ -469,6 +583,20 @@ class HipExec : public Executor {
   void precond(double* t, const double* r, const double* d, double theta, double eps, int64_t n) override {
     hipLaunchKernelGGL(precond_kernel, dim3(grid1(n)), dim3(256), 0, stream_, t, r, d, theta, eps, (long long)n);
     HIP_OK(hipGetLastError());
+  }
+  void sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes, int max_sweeps,
+               double tol) override {
+    if (offs.empty()) return;
+    long long* d_off = (long long*)alloc(offs.size() * sizeof(long long));
+    int* d_sz = (int*)alloc(sizes.size() * sizeof(int));
+    upload(d_off, offs.data(), offs.size() * sizeof(long long));
+    upload(d_sz, sizes.data(), sizes.size() * sizeof(int));
+    hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)offs.size()), dim3(256), 0, stream_, A, V, d_off, d_sz,
+                       max_sweeps, tol);
+    HIP_OK(hipGetLastError());
+    sync();
+    release(d_off);
+    release(d_sz);
   }
   hipStream_t stream() const { return stream_; }
 

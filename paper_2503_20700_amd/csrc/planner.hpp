@@ -218,7 +218,7 @@ class Context {
   std::vector<Bond> bonds;                 // bonds 0..n (left QNs up to k, right QNs from k+2)
   std::vector<SiteTensor> sites;           // size n (entries k, k+1 unused)
   std::unique_ptr<Block> Lblk, Rblk;       // blocks at bonds k and k+2
-  std::vector<std::unique_ptr<Block>> Lhist;  // left blocks kept per bond (optional)
+  std::vector<std::unique_ptr<Block>> Lhist, Rhist;  // blocks kept per bond (optional, indexed by bond)
 
   // building
   std::unique_ptr<Block> vacuum_left();

@@ -2,10 +2,14 @@
 // plan of the current two-site block and its device buffers.
 #pragma once
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "../../include/dmrg.h"
 #include "planner.hpp"
+
+// Record the thread-local error message returned by dmrg_last_error().
+int dmrg_fail(int code, const std::string& msg);
 
 // psi_in, psi_out, X, ones, diag placeholders used by the H*psi task lists
 enum { PH_IN = 1, PH_OUT = 2, PH_X = 3, PH_ONES = 4, PH_DIAG = 5 };
@@ -24,6 +28,10 @@ struct dmrg_ctx {
   // cut spectrum of the last truncation
   std::vector<double> cut_values;
   std::vector<int> cut_spins;
+  // Davidson workspace: basis V, images W (mmax x n each), x, Hx, r, t
+  std::vector<int> work_bufs;
+  int64_t work_n = 0;
+  int work_mmax = 0;
 
   ~dmrg_ctx() {
     reset_plan();
@@ -44,6 +52,10 @@ struct dmrg_ctx {
       p.ready = false;
     }
     if (C) {
+      for (int b : work_bufs) C->free_buf(b);
+      work_bufs.clear();
+      work_n = 0;
+      work_mmax = 0;
       for (int b : {b_in, b_out, b_x, b_ones, b_diag}) C->free_buf(b);
       if (C->Lblk) {
         for (auto& t : C->Lblk->tmp) C->free_buf(t.buf);

@@ -1,0 +1,117 @@
+"""GPU truncation (dmrg_truncate) and operator-block growth against the oracle.
+
+* The full multiplet spectrum of the cut, each weight w of spin S expanded to
+  2S+1 Schmidt values sqrt(w/(2S+1)), equals the oracle's Schmidt values from
+  an SVD of the explicit Fock-space wavefunction (singlet states).
+* With truncation to D multiplets, the kept weights are the D largest and
+  the reported error is the discarded fraction.
+* After truncation the grown operator block feeds H*psi at the next two-site
+  position; that H*psi equals the oracle's V^T H V psi for the MPS carrying
+  the new site tensor (both sweep directions).
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import heff
+from oracle import truncate as otr
+from synth.integrals import small_cas
+from synth.mps import left_site_blocks, psi_layout, random_mps, random_psi, right_site_blocks
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(case, keep=False):
+    from paper_2503_20700_amd.binding import DMRG
+    n, ne, ts, d, k, seed = case
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 10)
+    psi, lay = random_psi(mps, seed=seed + 20)
+    dm = DMRG(h, g, ne, ts, keep_blocks=keep)
+    bs, cnt = mps.bond_table()
+    dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+    return h, g, mps, psi, lay, dm
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_full_cut_spectrum_matches_fock_svd(direction):
+    h, g, mps, psi, lay, dm = _ctx((8, 8, 0, 64, 3, 0))
+    err, kept = dm.truncate(psi, 10 ** 6, 0.0, direction)
+    vals, spins = dm.cut_spectrum()
+    assert err < 1e-14
+    assert abs((vals ** 2).sum() - 1.0) < 1e-12
+    sv = otr.schmidt_values(mps, lay, psi)
+    expanded = np.sort(np.concatenate([np.full(s + 1, v / np.sqrt(s + 1)) for v, s in zip(vals, spins)]))[::-1]
+    m = len(expanded)
+    assert np.abs(expanded - sv[:m]).max() < 1e-12
+    assert (sv[m:] < 1e-12).all()
+
+
+def test_truncation_keeps_largest_weights():
+    h, g, mps, psi, lay, dm = _ctx((8, 8, 0, 64, 3, 0))
+    dm.truncate(psi, 10 ** 6, 0.0, 1)
+    full, _ = dm.cut_spectrum()
+    h, g, mps, psi, lay, dm = _ctx((8, 8, 0, 64, 3, 0))
+    err, kept = dm.truncate(psi, 12, 0.0, 1)
+    vals, _ = dm.cut_spectrum()
+    assert kept == 12
+    w = np.sort(full ** 2)[::-1]
+    assert np.abs(np.sort(vals ** 2)[::-1] - w[:12]).max() < 1e-12
+    assert abs(err - w[12:].sum()) < 1e-12
+    # truncation-error mode: smallest kept set with discarded weight <= eps
+    h, g, mps, psi, lay, dm = _ctx((8, 8, 0, 64, 3, 0))
+    eps = float(w[20:].sum()) * 1.000001
+    err2, kept2 = dm.truncate(psi, 10 ** 6, eps, 1)
+    assert kept2 == 20 and err2 <= eps
+
+
+def _moved_mps(mps, dm, k, direction):
+    m2 = copy.deepcopy(mps)
+    nb = dm.get_bond(k + 1)
+    if direction == 1:
+        a = dm.get_site(k)
+        blocks, off, lst = left_site_blocks(mps.left_bonds[k], nb), 0, []
+        for (il, s, ia) in blocks:
+            r, c = mps.left_bonds[k][il][2], nb[ia][2]
+            lst.append((il, s, ia, a[off:off + r * c].reshape(r, c)))
+            off += r * c
+        assert off == a.size
+        m2.left_bonds = mps.left_bonds[:k + 1] + [nb]
+        m2.A = mps.A + [lst]
+        m2.k = k + 1
+        m2.right_bonds = {b: v for b, v in mps.right_bonds.items() if b >= k + 3}
+        m2.B = {j: v for j, v in mps.B.items() if j >= k + 3}
+    else:
+        bt = dm.get_site(k + 1)
+        blocks, off, lst = right_site_blocks(nb, mps.right_bonds[k + 2]), 0, []
+        for (ic, s, ir) in blocks:
+            r, c = nb[ic][2], mps.right_bonds[k + 2][ir][2]
+            lst.append((ic, s, ir, bt[off:off + r * c].reshape(r, c)))
+            off += r * c
+        assert off == bt.size
+        m2.right_bonds = dict(mps.right_bonds)
+        m2.right_bonds[k + 1] = nb
+        m2.B = dict(mps.B)
+        m2.B[k + 1] = lst
+        m2.k = k - 1
+        m2.left_bonds = mps.left_bonds[:k]
+        m2.A = mps.A[:k - 1]
+    return m2
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+@pytest.mark.parametrize("case", [(8, 8, 0, 64, 3, 0), (8, 7, 1, 20, 3, 5)], ids=["s0", "s1/2"])
+def test_block_growth_after_truncation_matches_oracle(direction, case):
+    n, ne, ts, d, k, seed = case
+    h, g, mps, psi, lay, dm = _ctx(case, keep=True)
+    err, kept = dm.truncate(psi, 10, 0.0, direction)
+    assert dm.k == k + direction
+    m2 = _moved_mps(mps, dm, k, direction)
+    lay2 = psi_layout(m2.left_bonds[m2.k], m2.right_bonds[m2.k + 2], ne, ts)
+    p2 = np.random.default_rng(9).normal(size=sum(b["nrows"] * b["ncols"] for b in lay2))
+    he = heff.HeffDefinition(h, g, m2, lay2)
+    assert he.isometry_defect() < 1e-11
+    y, _ = dm.hpsi(p2)
+    ref = he.apply(p2)
+    assert np.abs(y - ref).max() < 1e-10 * np.abs(ref).max()

@@ -152,3 +152,22 @@ def test_heff_truncated_is_hermitian_and_variational():
     hd = he.dense()
     e_min = np.linalg.eigvalsh(0.5 * (hd + hd.T))[0]
     assert e_min >= fock.fci_spectrum(h, g, 8, 0)[0] - 1e-10
+
+
+def test_leading_csf_middle_cut_has_six_equal_schmidt_values():
+    # two S=5/2 fragments coupled to a singlet: sum_M (-1)^(5/2-M)/sqrt(6) |5/2 M>|5/2 -M>
+    from oracle import truncate as otr
+    path = [1, 2, 3, 4, 5, 4, 3, 2, 1, 0]
+    mps, lay, psi = _path_mps(path)
+    # cut between sites 8 and 9 of this MPS: the right part is one doublet, so
+    # the Schmidt values are those of |S=1/2 (x) 1/2 -> 0>: two equal values
+    sv = otr.schmidt_values(mps, lay, psi)
+    nz = sv[sv > 1e-12]
+    assert len(nz) == 2 and np.allclose(nz, 1 / np.sqrt(2))
+    # full Fock-space SVD across the 5|5 cut of the same state
+    from oracle.mps_fock import Embedding
+    full = Embedding(mps, lay).expand(psi)
+    mat = full.reshape(4 ** 5, 4 ** 5)  # index = left(sites 0..4) + 4^5 * right(sites 5..9)
+    s = np.linalg.svd(mat.T, compute_uv=False)
+    nz = s[s > 1e-12]
+    assert len(nz) == 6 and np.allclose(nz, 1 / np.sqrt(6))
