@@ -15,8 +15,10 @@
 // rounded while being staged into LDS); outputs are written in their own type.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <type_traits>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -76,23 +78,50 @@ __device__ __forceinline__ int acc_row(int lg, int v) {
   else return 4 * lg + v;
 }
 
+// Storage element of each dtype and its conversion to the arithmetic type.
+template <int DT> struct raw_of;
+template <> struct raw_of<DT_F64> { using T = double; };
+template <> struct raw_of<DT_F32> { using T = float; };
+template <> struct raw_of<DT_BF16> { using T = u16; };
+template <int DT, typename S>
+__device__ __forceinline__ S raw_to(typename raw_of<DT>::T r) {
+  if constexpr (DT == DT_BF16) return (S)bf2f(r);
+  else return (S)r;
+}
+
+// One unit of work of a launch: output tile (ti, tj) of job `job`, summing the
+// products [tbeg, tend) of that job.  slot < 0: the item owns the tile and
+// writes C; otherwise it writes its partial sum to partial slot `slot` and a
+// reduction launch adds the job's slots in order (deterministic split-K).
+struct WorkItem {
+  int job, ti, tj, tbeg, tend, slot;
+};
+struct RedItem {
+  int job, ti, tj, slot0, nslot, pad;
+};
+
 // MODE: DT_F64 / DT_F32 / DT_BF16 arithmetic; DA/DB/DC storage types.
+// The K loop is software-pipelined: the global loads of the next K slab
+// (which may belong to the next product) are issued into registers before the
+// MFMAs of the current slab, and LDS is double-buffered, so each K step has a
+// single barrier.
 template <int MODE, int DA, int DB, int DC>
 __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms,
-                                                   const int* __restrict__ tiles) {
+                                                   const WorkItem* __restrict__ items, void* __restrict__ part) {
   using acc_t = typename std::conditional<MODE == DT_F64, d4, f4>::type;
   using sc_t = typename std::conditional<MODE == DT_F64, double, float>::type;
+  using ra_t = typename raw_of<DA>::T;
+  using rb_t = typename raw_of<DB>::T;
   constexpr int KT = (MODE == DT_BF16) ? 32 : 16;
   // F64/F32: LDS k-major [KT][TM+1]; BF16: row-major [TM][KT+8] of bf16 bits
   constexpr int LDS_A = (MODE == DT_BF16) ? TM * (KT + 8) * 2 : KT * (TM + 1) * (MODE == DT_F64 ? 8 : 4);
-  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * LDS_A];
-  unsigned char* sA = smem;
-  unsigned char* sB = smem + LDS_A;
+  constexpr int PER = TM * KT / 256;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[4 * LDS_A];
 
   const int tid = threadIdx.x;
-  const int job = tiles[3 * blockIdx.x], ti = tiles[3 * blockIdx.x + 1], tj = tiles[3 * blockIdx.x + 2];
-  const RawJob J = jobs[job];
-  const int m0 = ti * TM, n0 = tj * TN;
+  const WorkItem W = items[blockIdx.x];
+  const RawJob J = jobs[W.job];
+  const int m0 = W.ti * TM, n0 = W.tj * TN;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lg = lane >> 4;
@@ -105,104 +134,161 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
 
-  for (long long t = J.tbeg; t < J.tend; ++t) {
+  // ---- identity products: C += alpha * (the other operand), read at this
+  // lane's accumulator positions.
+  for (int t = W.tbeg; t < W.tend; ++t) {
+    const int fl = terms[t].flags;
+    if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+    const RawTerm T = terms[t];
+    const bool ia = fl & TF_IDENT_A;
+    const void* P = ia ? T.B : T.A;
+    const long long ld = ia ? T.ldb : T.lda;
+    const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = m0 + wm + a * 16 + acc_row<MODE>(lg, v);
+          const int col = n0 + wn + b * 16 + lr;
+          if (row < J.m && col < J.n) {
+            const long long idx = tr ? (long long)col * ld + row : (long long)row * ld + col;
+            const double x = ia ? ldv<DB>(P, idx) : ldv<DA>(P, idx);
+            acc[a][b][v] += (sc_t)(T.alpha * x);
+          }
+        }
+  }
+
+  // ---- dense products, pipelined over the flattened (product, k0) sequence
+  auto next_dense = [&](int t) {
+    while (t < W.tend && (terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) ++t;
+    return t;
+  };
+  ra_t ra[PER];
+  rb_t rb[PER];
+  sc_t ralpha = 0;
+  auto load = [&](int t, int k0) {
     const RawTerm T = terms[t];
     const int K = T.k;
-    if (T.flags & (TF_IDENT_A | TF_IDENT_B)) {
-      // C += alpha * (the other operand): read it at this lane's accumulator positions.
-      const bool ia = T.flags & TF_IDENT_A;
-      const void* P = ia ? T.B : T.A;
-      const long long ld = ia ? T.ldb : T.lda;
-      const bool tr = ia ? (T.flags & TF_TRANS_B) : (T.flags & TF_TRANS_A);
+    const bool ta = T.flags & TF_TRANS_A, tb = T.flags & TF_TRANS_B;
+    ralpha = (sc_t)T.alpha;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int idx = tid + 256 * r;
+      int i, kk;
+      if (!ta) { i = idx / KT; kk = idx % KT; } else { kk = idx / TM; i = idx % TM; }
+      const int gi = m0 + i, gk = k0 + kk;
+      ra[r] = 0;
+      if (gi < J.m && gk < K) ra[r] = ((const ra_t*)T.A)[ta ? (long long)gk * T.lda + gi : (long long)gi * T.lda + gk];
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int idx = tid + 256 * r;
+      int j, kk;
+      if (!tb) { kk = idx / TN; j = idx % TN; } else { j = idx / KT; kk = idx % KT; }
+      const int gj = n0 + j, gk = k0 + kk;
+      rb[r] = 0;
+      if (gj < J.n && gk < K) rb[r] = ((const rb_t*)T.B)[tb ? (long long)gj * T.ldb + gk : (long long)gk * T.ldb + gj];
+    }
+  };
+  // The LDS position of register r depends on the product's transposition
+  // flags, which are kept with the registers.
+  int rflags = 0;
+  auto store = [&](unsigned char* sA, unsigned char* sB) {
+    const bool ta = rflags & TF_TRANS_A, tb = rflags & TF_TRANS_B;
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int idx = tid + 256 * r;
+      int i, kk;
+      if (!ta) { i = idx / KT; kk = idx % KT; } else { kk = idx / TM; i = idx % TM; }
+      const sc_t v = raw_to<DA, sc_t>(ra[r]) * ralpha;
+      if constexpr (MODE == DT_BF16) ((u16*)sA)[i * (KT + 8) + kk] = f2bf(v);
+      else ((sc_t*)sA)[kk * (TM + 1) + i] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int idx = tid + 256 * r;
+      int j, kk;
+      if (!tb) { kk = idx / TN; j = idx % TN; } else { j = idx / KT; kk = idx % KT; }
+      const sc_t v = raw_to<DB, sc_t>(rb[r]);
+      if constexpr (MODE == DT_BF16) ((u16*)sB)[j * (KT + 8) + kk] = f2bf(v);
+      else ((sc_t*)sB)[kk * (TN + 1) + j] = v;
+    }
+  };
+  auto compute = [&](const unsigned char* sA, const unsigned char* sB) {
+    if constexpr (MODE == DT_BF16) {
+      bf8 av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = *(const bf8*)&((const u16*)sA)[(wm + a * 16 + lr) * (KT + 8) + 8 * lg];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = *(const bf8*)&((const u16*)sB)[(wn + b * 16 + lr) * (KT + 8) + 8 * lg];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    } else {
+      const sc_t* A_ = (const sc_t*)sA;
+      const sc_t* B_ = (const sc_t*)sB;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = m0 + wm + a * 16 + acc_row<MODE>(lg, v);
-            const int col = n0 + wn + b * 16 + lr;
-            if (row < J.m && col < J.n) {
-              const long long idx = tr ? (long long)col * ld + row : (long long)row * ld + col;
-              const double x = ia ? ldv<DB>(P, idx) : ldv<DA>(P, idx);
-              acc[a][b][v] += (sc_t)(T.alpha * x);
-            }
-          }
-      continue;
+      for (int kk = 0; kk < KT; kk += 4) {
+        const sc_t a0 = A_[(kk + lg) * (TM + 1) + wm + lr];
+        const sc_t a1 = A_[(kk + lg) * (TM + 1) + wm + 16 + lr];
+        const sc_t b0 = B_[(kk + lg) * (TN + 1) + wn + lr];
+        const sc_t b1 = B_[(kk + lg) * (TN + 1) + wn + 16 + lr];
+        if constexpr (MODE == DT_F64) {
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        } else {
+          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+      }
     }
-    const bool ta = T.flags & TF_TRANS_A, tb = T.flags & TF_TRANS_B;
-    const sc_t alpha = (sc_t)T.alpha;
-    for (int k0 = 0; k0 < K; k0 += KT) {
-      // ---- stage A (TM x KT) and B (KT x TN) into LDS
-      constexpr int PER = TM * KT / 256;
-#pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int idx = tid + 256 * r;
-        int i, kk;
-        if (!ta) { i = idx / KT; kk = idx % KT; } else { kk = idx / TM; i = idx % TM; }
-        const int gi = m0 + i, gk = k0 + kk;
-        sc_t v = 0;
-        if (gi < J.m && gk < K) {
-          const long long g = ta ? (long long)gk * T.lda + gi : (long long)gi * T.lda + gk;
-          if constexpr (MODE == DT_F64) v = (sc_t)ldv<DA>(T.A, g) * alpha;
-          else v = ldf<DA>(T.A, g) * alpha;
-        }
-        if constexpr (MODE == DT_BF16) ((u16*)sA)[i * (KT + 8) + kk] = f2bf(v);
-        else ((sc_t*)sA)[kk * (TM + 1) + i] = v;
-      }
-#pragma unroll
-      for (int r = 0; r < PER; ++r) {
-        const int idx = tid + 256 * r;
-        int j, kk;
-        if (!tb) { kk = idx / TN; j = idx % TN; } else { j = idx / KT; kk = idx % KT; }
-        const int gj = n0 + j, gk = k0 + kk;
-        sc_t v = 0;
-        if (gj < J.n && gk < K) {
-          const long long g = tb ? (long long)gj * T.ldb + gk : (long long)gk * T.ldb + gj;
-          if constexpr (MODE == DT_F64) v = (sc_t)ldv<DB>(T.B, g);
-          else v = ldf<DB>(T.B, g);
-        }
-        if constexpr (MODE == DT_BF16) ((u16*)sB)[j * (KT + 8) + kk] = f2bf(v);
-        else ((sc_t*)sB)[kk * (TN + 1) + j] = v;
-      }
-      __syncthreads();
-      // ---- MFMA
-      if constexpr (MODE == DT_BF16) {
-        bf8 av[2], bv[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = *(const bf8*)&((const u16*)sA)[(wm + a * 16 + lr) * (KT + 8) + 8 * lg];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) bv[b] = *(const bf8*)&((const u16*)sB)[(wn + b * 16 + lr) * (KT + 8) + 8 * lg];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < KT; kk += 4) {
-          const sc_t* A_ = (const sc_t*)sA;
-          const sc_t* B_ = (const sc_t*)sB;
-          sc_t a0 = A_[(kk + lg) * (TM + 1) + wm + lr];
-          sc_t a1 = A_[(kk + lg) * (TM + 1) + wm + 16 + lr];
-          sc_t b0 = B_[(kk + lg) * (TN + 1) + wn + lr];
-          sc_t b1 = B_[(kk + lg) * (TN + 1) + wn + 16 + lr];
-          if constexpr (MODE == DT_F64) {
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-          } else {
-            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
-          }
-        }
-      }
-      __syncthreads();
-    }
+  };
+
+  int t = next_dense(W.tbeg), k0 = 0;
+  if (t < W.tend) {
+    load(t, k0);
+    rflags = terms[t].flags;
   }
-  // ---- write back (row = 4*lg + v, col = lr inside each 16x16 block)
+  int buf = 0;
+  while (t < W.tend) {
+    unsigned char* sA = smem + buf * 2 * LDS_A;
+    unsigned char* sB = sA + LDS_A;
+    store(sA, sB);
+    __syncthreads();
+    int t2 = t, k2 = k0 + KT;
+    if (k2 >= terms[t].k) {
+      t2 = next_dense(t + 1);
+      k2 = 0;
+    }
+    if (t2 < W.tend) {
+      load(t2, k2);
+      rflags = terms[t2].flags;
+    }
+    compute(sA, sB);
+    buf ^= 1;
+    t = t2;
+    k0 = k2;
+  }
+
+  // ---- write back
+  if (W.slot >= 0) {
+    sc_t* P = (sc_t*)part + (long long)W.slot * (TM * TN);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          P[(wm + a * 16 + acc_row<MODE>(lg, v)) * TN + wn + b * 16 + lr] = acc[a][b][v];
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -221,6 +307,29 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
           }
         }
       }
+}
+
+// Sum of the partial tiles of split items, in slot order, into C.
+template <int MODE, int DC>
+__global__ __launch_bounds__(256) void reduce_kernel(const RawJob* __restrict__ jobs, const RedItem* __restrict__ items,
+                                                     const void* __restrict__ part) {
+  using sc_t = typename std::conditional<MODE == DT_F64, double, float>::type;
+  const RedItem R = items[blockIdx.x];
+  const RawJob J = jobs[R.job];
+  const sc_t* P = (const sc_t*)part + (long long)R.slot0 * (TM * TN);
+  for (int e = threadIdx.x; e < TM * TN; e += 256) {
+    const int row = R.ti * TM + e / TN, col = R.tj * TN + e % TN;
+    if (row >= J.m || col >= J.n) continue;
+    sc_t s = 0;
+    for (int q = 0; q < R.nslot; ++q) s += P[(long long)q * (TM * TN) + e];
+    const long long o = (long long)row * J.ldc + col;
+    if (J.accumulate) {
+      if constexpr (DC == DT_F64) ((double*)J.C)[o] += (double)s;
+      else stv<DC>(J.C, o, ldv<DC>(J.C, o) + (double)s);
+    } else {
+      stv<DC>(J.C, o, s);
+    }
+  }
 }
 
 template <int DS, int DD>
@@ -412,12 +521,14 @@ __global__ __launch_bounds__(256) void jacobi_kernel(double* __restrict__ Aall, 
 struct Prepared {
   RawJob* d_jobs = nullptr;
   RawTerm* d_terms = nullptr;
-  int* d_tiles = nullptr;
-  long long ntiles = 0;
+  WorkItem* d_items = nullptr;
+  RedItem* d_reds = nullptr;
+  long long nitems = 0, nreds = 0, nslots = 0;
   int mode = DT_F64, da = DT_F64, db = DT_F64, dc = DT_F64;
 };
 
-using KernelFn = void (*)(const RawJob*, const RawTerm*, const int*);
+using KernelFn = void (*)(const RawJob*, const RawTerm*, const WorkItem*, void*);
+using ReduceFn = void (*)(const RawJob*, const RedItem*, const void*);
 
 KernelFn pick(int mode, int da, int db, int dc) {
 #define K_(M, A, B, C) \
@@ -429,11 +540,82 @@ KernelFn pick(int mode, int da, int db, int dc) {
 #undef K_
   throw std::runtime_error("executor: unsupported dtype combination");
 }
+ReduceFn pick_reduce(int mode, int dc) {
+  if (mode == DT_F64 && dc == DT_F64) return reduce_kernel<DT_F64, DT_F64>;
+  if (mode != DT_F64 && dc == DT_F32) return reduce_kernel<DT_F32, DT_F32>;
+  if (mode != DT_F64 && dc == DT_BF16) return reduce_kernel<DT_F32, DT_BF16>;
+  throw std::runtime_error("executor: unsupported reduction dtype");
+}
+
+// Work decomposition of one launch.  The cost of a tile is its number of K
+// steps (one per KT slice of each dense product, half a step per identity
+// product).  Tiles whose cost exceeds a target are cut between products into
+// several items that write partial tiles; the target is chosen so that the
+// launch has at least ~16k items (enough to fill 256 CUs several times over)
+// but never below 64 steps.  Items are issued heaviest first (longest
+// processing time first), which bounds the tail of the launch.
+void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int kt, std::vector<WorkItem>& items,
+                std::vector<RedItem>& reds, long long& nslots) {
+  std::vector<double> pcost(terms.size());
+  for (size_t t = 0; t < terms.size(); ++t)
+    pcost[t] = (terms[t].flags & (TF_IDENT_A | TF_IDENT_B)) ? 0.5 : (double)((terms[t].k + kt - 1) / kt);
+  double total = 0.0;
+  for (const RawJob& J : jobs) {
+    double c = 0.0;
+    for (int64_t t = J.tbeg; t < J.tend; ++t) c += pcost[t];
+    total += c * (double)((J.m + TM - 1) / TM) * (double)((J.n + TN - 1) / TN);
+  }
+  double target = std::max(64.0, total / 16384.0);
+  // DMRG_SPLIT_STEPS overrides the target (tuning and tests of the split path)
+  if (const char* e = std::getenv("DMRG_SPLIT_STEPS")) {
+    const double v = std::atof(e);
+    if (v > 0.0) target = v;
+  }
+  std::vector<std::pair<double, WorkItem>> work;
+  nslots = 0;
+  reds.clear();
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    const RawJob& J = jobs[j];
+    if (J.m <= 0 || J.n <= 0) continue;
+    // cut points of the product list (shared by all tiles of the job)
+    std::vector<std::pair<int, int>> segs;
+    std::vector<double> scost;
+    double c = 0.0;
+    int64_t s0 = J.tbeg;
+    for (int64_t t = J.tbeg; t < J.tend; ++t) {
+      c += pcost[t];
+      if (c >= target && t + 1 < J.tend) {
+        segs.push_back({(int)s0, (int)(t + 1)});
+        scost.push_back(c);
+        s0 = t + 1;
+        c = 0.0;
+      }
+    }
+    segs.push_back({(int)s0, (int)J.tend});
+    scost.push_back(c);
+    const int tm = (J.m + TM - 1) / TM, tn = (J.n + TN - 1) / TN;
+    for (int a = 0; a < tm; ++a)
+      for (int b = 0; b < tn; ++b) {
+        if (segs.size() == 1) {
+          work.push_back({scost[0], WorkItem{(int)j, a, b, segs[0].first, segs[0].second, -1}});
+          continue;
+        }
+        reds.push_back(RedItem{(int)j, a, b, (int)nslots, (int)segs.size(), 0});
+        for (size_t q = 0; q < segs.size(); ++q)
+          work.push_back({scost[q], WorkItem{(int)j, a, b, segs[q].first, segs[q].second, (int)(nslots + q)}});
+        nslots += (long long)segs.size();
+      }
+  }
+  std::stable_sort(work.begin(), work.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  items.resize(work.size());
+  for (size_t i = 0; i < work.size(); ++i) items[i] = work[i].second;
+}
 
 class HipExec : public Executor {
  public:
   HipExec() { HIP_OK(hipStreamCreate(&stream_)); }
   ~HipExec() override {
+    if (part_) (void)hipFree(part_);
     if (dot_part_) (void)hipFree(dot_part_);
     if (dot_out_) (void)hipFree(dot_out_);
     for (auto& e : events_) {
@@ -473,44 +655,61 @@ class HipExec : public Executor {
     P->db = db;
     P->dc = dc;
     P->mode = (da == DT_F64) ? DT_F64 : (da == DT_F32 ? DT_F32 : DT_BF16);
-    std::vector<int> tiles;
-    for (size_t j = 0; j < jobs.size(); ++j) {
-      const int tm = (jobs[j].m + TM - 1) / TM, tn = (jobs[j].n + TN - 1) / TN;
-      for (int a = 0; a < tm; ++a)
-        for (int b = 0; b < tn; ++b) {
-          tiles.push_back((int)j);
-          tiles.push_back(a);
-          tiles.push_back(b);
-        }
-    }
-    P->ntiles = (long long)tiles.size() / 3;
-    if (P->ntiles) {
+    pick(P->mode, da, db, dc);  // validate
+    if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
+    std::vector<WorkItem> items;
+    std::vector<RedItem> reds;
+    plan_items(jobs, terms, P->mode == DT_BF16 ? 32 : 16, items, reds, P->nslots);
+    P->nitems = (long long)items.size();
+    P->nreds = (long long)reds.size();
+    if (P->nreds) pick_reduce(P->mode, dc);
+    if (P->nitems) {
       P->d_jobs = (RawJob*)alloc(jobs.size() * sizeof(RawJob));
       P->d_terms = (RawTerm*)alloc(std::max<size_t>(terms.size(), 1) * sizeof(RawTerm));
-      P->d_tiles = (int*)alloc(tiles.size() * sizeof(int));
+      P->d_items = (WorkItem*)alloc(items.size() * sizeof(WorkItem));
       upload(P->d_jobs, jobs.data(), jobs.size() * sizeof(RawJob));
       if (!terms.empty()) upload(P->d_terms, terms.data(), terms.size() * sizeof(RawTerm));
-      upload(P->d_tiles, tiles.data(), tiles.size() * sizeof(int));
+      upload(P->d_items, items.data(), items.size() * sizeof(WorkItem));
+      if (P->nreds) {
+        P->d_reds = (RedItem*)alloc(reds.size() * sizeof(RedItem));
+        upload(P->d_reds, reds.data(), reds.size() * sizeof(RedItem));
+      }
     }
-    pick(P->mode, da, db, dc);  // validate
+    const size_t need = (size_t)P->nslots * TM * TN * (P->mode == DT_F64 ? 8 : 4);
+    if (need > part_bytes_) {
+      sync();
+      if (part_) release(part_);
+      part_ = nullptr;
+      part_bytes_ = 0;
+      part_ = alloc(need);
+      part_bytes_ = need;
+    }
     return P;
   }
   void run(void* h) override {
     auto* P = (Prepared*)h;
-    if (!P->ntiles) return;
+    if (!P->nitems) return;
     KernelFn k = pick(P->mode, P->da, P->db, P->dc);
-    const long long maxg = 0x7fffffffLL;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing_) {
       HIP_OK(hipEventCreate(&e0));
       HIP_OK(hipEventCreate(&e1));
       HIP_OK(hipEventRecord(e0, stream_));
     }
-    for (long long t0 = 0; t0 < P->ntiles; t0 += maxg) {
-      const long long nt = std::min(maxg, P->ntiles - t0);
-      hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_tiles + 3 * t0);
+    const long long maxg = 0x7fffffffLL;
+    for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
+      const long long nt = std::min(maxg, P->nitems - t0);
+      hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0, part_);
     }
     HIP_OK(hipGetLastError());
+    if (P->nreds) {
+      ReduceFn r = pick_reduce(P->mode, P->dc);
+      for (long long t0 = 0; t0 < P->nreds; t0 += maxg) {
+        const long long nt = std::min(maxg, P->nreds - t0);
+        hipLaunchKernelGGL(r, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_reds + t0, part_);
+      }
+      HIP_OK(hipGetLastError());
+    }
     if (timing_) {
       HIP_OK(hipEventRecord(e1, stream_));
       events_.push_back({e0, e1});
@@ -541,7 +740,8 @@ class HipExec : public Executor {
     HIP_OK(hipStreamSynchronize(stream_));
     release(P->d_jobs);
     release(P->d_terms);
-    release(P->d_tiles);
+    release(P->d_items);
+    release(P->d_reds);
     delete P;
   }
   void sync() override { HIP_OK(hipStreamSynchronize(stream_)); }
@@ -602,6 +802,8 @@ class HipExec : public Executor {
 
  private:
   static unsigned grid1(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+  void* part_ = nullptr;  // partial tiles of split items, shared by all launches
+  size_t part_bytes_ = 0;
   double* dot_part_ = nullptr;
   double* dot_out_ = nullptr;
   hipStream_t stream_ = nullptr;

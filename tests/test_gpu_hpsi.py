@@ -90,3 +90,21 @@ def test_hermiticity_fp64():
     hy, _ = dm.hpsi(y)
     lhs, rhs = x @ hy, hx @ y
     assert abs(lhs - rhs) < 1e-12 * np.linalg.norm(hx) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("steps", ["1", "3"])
+def test_hpsi_split_k_matches_oracle(steps, monkeypatch):
+    # Force the executor to cut every output tile's product list into pieces
+    # of at most `steps` K steps, so that nearly every tile is summed from
+    # partial tiles by the reduction launch (block builds included).
+    monkeypatch.setenv("DMRG_SPLIT_STEPS", steps)
+    case = (10, 10, 0, 40, 4, 6)
+    print(f"[hpsi split-K] steps={steps} case={case}", flush=True)
+    h, g, mps, psi, lay, dm = _setup(*case)
+    y, _ = dm.hpsi(psi)
+    ref = heff.hpsi(h, g, mps, lay, psi)
+    assert np.abs(y - ref).max() < 1e-10 * np.abs(ref).max()
+    y2, _ = dm.hpsi(psi)
+    assert np.array_equal(y, y2)
+    ylo, _ = dm.hpsi(psi, 2)
+    assert np.abs(ylo - ref).max() < 2.0 ** -8 * 8 * np.abs(ref).max()
