@@ -77,6 +77,33 @@ def cpu_baseline(lib_flops_fn):
                       f"{reps} reps after 1 warm-up, {dt * 1e3:.0f} ms each"}
 
 
+def accuracy_case(DMRG, BF16, FP64):
+    """Mixed precision against the FP64 path where both Davidson runs converge
+    to the paper's residual (1e-7): the centre two-site block of CAS(10,10),
+    S=0, D=1000 (complete two-site space, 19,404 coefficients), same start
+    vector.  Returns the two energies, |dE| and the matvec counts."""
+    from synth.integrals import small_cas
+    from synth.mps import random_mps, random_psi
+    h, g, _ = small_cas(10, 21)
+    mps = random_mps(10, 10, 0, 1000, k=4, seed=21)
+    psi, _ = random_psi(mps, seed=22)
+    out = {}
+    for name, prec in (("bf16+fp64", BF16), ("fp64", FP64)):
+        d = DMRG(h, g, 10, 0, hpsi_prec=prec, davidson_max_iter=400)
+        b, c = mps.bond_table()
+        d.set_mps(4, b, c, mps.site_blocks_flat())
+        r = d.davidson(psi)
+        d.close()
+        out[name] = r
+    e_mix, e_64 = out["bf16+fp64"]["energy"], out["fp64"]["energy"]
+    return {"workload": "CAS(10,10) S=0 centre block, complete two-site space (19404 coefficients)",
+            "energy_mixed": e_mix, "energy_fp64": e_64, "abs_dE_Eh": abs(e_mix - e_64),
+            "resid_mixed": out["bf16+fp64"]["resid"], "resid_fp64": out["fp64"]["resid"],
+            "matvecs_mixed": {"bf16": out["bf16+fp64"]["n_lo"], "fp64": out["bf16+fp64"]["n_fp64"]},
+            "matvecs_fp64": out["fp64"]["n_fp64"],
+            "converged": bool(out["bf16+fp64"]["converged"] and out["fp64"]["converged"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,61 +111,111 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default=os.environ.get("DMRG_BENCH_CONFIG", "cfg4"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dmrg-step", action="store_true", help="skip the timed Davidson + truncation step")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the converged mixed-vs-FP64 case")
+    ap.add_argument("--dav-lo", type=int, default=8, help="BF16 Davidson iterations in the DMRG step")
+    ap.add_argument("--dav-hi", type=int, default=3, help="FP64 refinement iterations in the DMRG step")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
+    import torch
     from paper_2503_20700_amd.binding import BF16, DMRG, FP64
     from synth.mps import random_mps, random_psi
 
+    dev = torch.device("cuda:0")
     w = workload(args.config)
     t0 = time.perf_counter()
     mps = random_mps(w["n"], w["N"], w["two_s"], w["D"], k=w["k"], seed=w["seed"])
     psi, lay = random_psi(mps, seed=w["seed"] + 1)
     log(f"{w['name']}: MPS drawn in {time.perf_counter() - t0:.1f}s, psi has {psi.size} coefficients")
-    dm = DMRG(w["h"], w["g"], w["N"], w["two_s"])
+    dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=BF16, davidson_max_iter=args.dav_lo,
+              davidson_refine_iter=args.dav_hi)
     bs, cnt = mps.bond_table()
     t0 = time.perf_counter()
     dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())
     t_env = time.perf_counter() - t0
     log(f"operator blocks built in {t_env:.1f}s")
     t0 = time.perf_counter()
-    y64, flops = dm.hpsi(psi, FP64)   # plans the H*psi task lists, first FP64 matvec
+    y64_host, flops = dm.hpsi(psi, FP64)   # plans the H*psi task lists, first FP64 matvec
     t_plan = time.perf_counter() - t0
     st = dm.stats()
     log(f"H*psi planned ({st['n_terms']} terms, {st['n_tasks']} block products, {flops:.3e} flop) in {t_plan:.1f}s")
 
-    def step():
-        ylo, _ = dm.hpsi(psi, BF16)
-        y, _ = dm.hpsi(psi, FP64)
-        return ylo, y
+    # inputs resident in HBM before timing
+    x = torch.from_numpy(psi).to(dev)
+    ylo = torch.empty_like(x)
+    yhi = torch.empty_like(x)
+
+    def hpsi(prec, out):
+        dm.hpsi_dev(x.data_ptr(), out.data_ptr(), prec)
+        torch.cuda.synchronize()
 
     for i in range(args.warmup):
-        step()
+        hpsi(BF16, ylo)
+        hpsi(FP64, yhi)
         log(f"warm-up {i + 1}/{args.warmup} done")
-    # timed region: BF16 and FP64 matvecs, with device-event timing of every GEMM launch
-    t_lo = t_hi = 0.0
-    n_lo = n_hi = 0
+    # timed region: one BF16 (bulk Davidson) and one FP64 (refinement) H*psi per step
+    t_lo = t_hi = k_lo = k_hi = 0.0
+    n_lo = 0
+    torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
         dm.kernel_timing(1)
-        ylo, _ = dm.hpsi(psi, BF16)
+        t0 = time.perf_counter()
+        hpsi(BF16, ylo)
+        t_lo += time.perf_counter() - t0
         ms, nl = dm.kernel_timing(0)
-        t_lo += ms
+        k_lo += ms
         n_lo += nl
         dm.kernel_timing(1)
-        y, _ = dm.hpsi(psi, FP64)
-        ms, nl = dm.kernel_timing(0)
-        t_hi += ms
-        n_hi += nl
-        log(f"step {i + 1}/{args.steps}: bf16 {t_lo / (i + 1):.1f} ms, fp64 {t_hi / (i + 1):.1f} ms of kernels")
+        t0 = time.perf_counter()
+        hpsi(FP64, yhi)
+        t_hi += time.perf_counter() - t0
+        ms, _ = dm.kernel_timing(0)
+        k_hi += ms
+        log(f"step {i + 1}/{args.steps}: bf16 {t_lo / (i + 1) * 1e3:.1f} ms, fp64 {t_hi / (i + 1) * 1e3:.1f} ms")
+    torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_start
-    ms_step = t_wall / args.steps * 1e3
-    lo_tflops = flops * args.steps / (t_lo * 1e-3) / 1e12
-    hi_tflops = flops * args.steps / (t_hi * 1e-3) / 1e12
-    rel = float(np.abs(ylo - y).max() / np.abs(y).max())
-    e_lo, e_hi = float(psi @ ylo), float(psi @ y)
+    K = max(args.steps, 1)
+    lo_tflops = flops * K / t_lo / 1e12
+    hi_tflops = flops * K / t_hi / 1e12
+    lo_kernel_tflops = flops * K / (k_lo * 1e-3) / 1e12
+    hi_kernel_tflops = flops * K / (k_hi * 1e-3) / 1e12
+    ylo_h, yhi_h = ylo.cpu().numpy(), yhi.cpu().numpy()
+    rel = float(np.abs(ylo_h - yhi_h).max() / np.abs(yhi_h).max())
+    e_lo, e_hi = float(psi @ ylo_h), float(psi @ yhi_h)
+    # full-size property checks (FP64): reproducibility and Hermiticity <phi|H psi> = <H phi|psi>
+    phi = np.random.default_rng(7).normal(size=psi.size)
+    hphi, _ = dm.hpsi(phi, FP64)
+    herm = abs(phi @ yhi_h - hphi @ psi) / (np.linalg.norm(phi) * np.linalg.norm(yhi_h))
+    repro = bool(np.array_equal(yhi_h, y64_host))
+
+    step = None
+    if not args.no_dmrg_step:
+        # One two-site DMRG step at the centre: Davidson (BF16 bulk matvecs, then
+        # FP64 refinement matvecs, fixed iteration budgets), truncation to D
+        # multiplets, growth of the left operator block across the new bond.
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = dm.davidson(psi)
+        t1 = time.perf_counter()
+        err, kept = dm.truncate(r["psi"], w["D"], 0.0, 1)
+        t2 = time.perf_counter()
+        step = {"seconds": t2 - t0, "davidson_s": t1 - t0, "truncate_and_grow_s": t2 - t1,
+                "matvecs": {"bf16": r["n_lo"], "fp64": r["n_fp64"]}, "energy_Eh": r["energy"],
+                "residual": r["resid"], "residual_target": 1e-7, "converged": r["converged"],
+                "budget": {"bf16_iters": args.dav_lo, "fp64_iters": args.dav_hi},
+                "trunc_err": err, "d_kept": kept,
+                "start_vector": "random (no previous step to warm-start from)"}
+        log(f"DMRG step: {step['seconds']:.1f}s (Davidson {step['davidson_s']:.1f}s, "
+            f"truncation + growth {step['truncate_and_grow_s']:.1f}s), residual {r['resid']:.2e}")
+
+    acc = None
+    if not args.no_accuracy:
+        log("converged mixed-vs-FP64 case")
+        acc = accuracy_case(DMRG, BF16, FP64)
 
     base = None
     if not args.no_cpu_baseline:
@@ -159,7 +236,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": t_wall / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -167,15 +244,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "n_orb": w["n"], "n_elec": w["N"], "two_s": w["two_s"], "D": w["D"],
                    "two_site_block": [w["k"], w["k"] + 1], "psi_len": int(psi.size)},
-        "roofline": {"bound": "mfma", "achieved": lo_tflops, "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                     "frac": lo_tflops / PEAK["bf16"], "traffic": None},
+        "roofline": {"bound": "mfma", "achieved": lo_kernel_tflops, "peak": PEAK["bf16"], "unit": "TFLOP/s",
+                     "frac": lo_kernel_tflops / PEAK["bf16"], "traffic": None},
         "cpu_baseline": base,
         "hpsi_flops": flops,
-        "fp64": {"tflops": hi_tflops, "roofline_frac": hi_tflops / PEAK["f64"], "ms_per_hpsi": t_hi / args.steps},
-        "bf16": {"ms_per_hpsi": t_lo / args.steps, "launches_per_hpsi": n_lo // max(args.steps, 1)},
+        "bf16": {"ms_per_hpsi": t_lo / K * 1e3, "kernel_ms_per_hpsi": k_lo / K, "launches_per_hpsi": n_lo // K},
+        "fp64": {"tflops": hi_tflops, "kernel_tflops": hi_kernel_tflops, "roofline_frac": hi_kernel_tflops / PEAK["f64"],
+                 "ms_per_hpsi": t_hi / K * 1e3, "kernel_ms_per_hpsi": k_hi / K},
         "speedup_bf16_vs_fp64": t_hi / t_lo if t_lo > 0 else None,
         "rel_err_bf16_vs_fp64": rel,
         "rayleigh_bf16_minus_fp64_Eh": e_lo - e_hi,
+        "fp64_hermiticity_rel": float(herm),
+        "fp64_bitwise_reproducible": repro,
+        "dmrg_step": step,
+        "accuracy_mixed_vs_fp64": acc,
         "setup_s": {"operator_blocks": t_env, "hpsi_plan": t_plan},
         "op_bytes_f64": st["op_bytes"],
         "peak_device_bytes": st["peak_bytes"],

@@ -74,6 +74,8 @@ typedef struct {
   int keep_blocks;             /* 1: keep the operator blocks of every bond that
                                   dmrg_set_mps builds, so dmrg_truncate can move
                                   the two-site block (memory grows with n)        */
+  int davidson_refine_iter;    /* iterations of the FP64 refinement phase when
+                                  hpsi_prec is not FP64; 0: davidson_max_iter     */
 } dmrg_opts;
 
 /* Create a context; copies h (n*n) and g (n^4).  Errors: ARG, SYMMETRY

@@ -255,7 +255,9 @@ extern "C" int dmrg_davidson_step(dmrg_ctx* c, int k, double* psi, double* energ
       lo = pr.matvecs;
     }
     // phase 2 (or the whole solve for FP64): FP64 matvecs to tol
-    pr = davidson_phase(c, ws, DMRG_FP64, tol, max_iter);
+    const int refine_iter =
+        (prec != DMRG_FP64 && c->opts.davidson_refine_iter > 0) ? c->opts.davidson_refine_iter : max_iter;
+    pr = davidson_phase(c, ws, DMRG_FP64, tol, refine_iter);
     hi = pr.matvecs;
     c->ex->download(psi, c->C->ptr(ws.bx), (size_t)n * 8);
     *energy = pr.theta + c->opts.e_core;
@@ -352,9 +354,20 @@ extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int
       j.tend = (int64_t)gb.terms.size();
       gb.jobs.push_back(j);
     }
+    const bool verbose = std::getenv("DMRG_VERBOSE") != nullptr;
+    auto tick = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what) {
+      if (!verbose) return;
+      ex->sync();
+      auto now = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "[truncate] %s %.3f s\n", what, std::chrono::duration<double>(now - tick).count());
+      tick = now;
+    };
     c->bind();
     C.run_batch(gb);
+    lap("rho");
     ex->sym_eig((double*)C.ptr(bR), (double*)C.ptr(bV), offs, sizes, 40, 1e-15);
+    lap("eigensolve");
     std::vector<double> hR((size_t)tot), hV((size_t)tot);
     ex->download(hR.data(), C.ptr(bR), (size_t)tot * 8);
     ex->download(hV.data(), C.ptr(bV), (size_t)tot * 8);
@@ -494,6 +507,7 @@ extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int
     }
     T.buf = C.new_buf(std::max<int64_t>((int64_t)vals.size(), 1));
     if (!vals.empty()) ex->upload(C.ptr(T.buf), vals.data(), vals.size() * 8);
+    lap("select + site tensor");
     // ---- grow the operator block across the cut, move the two-site block if possible
     c->reset_plan();
     const bool keep = c->opts.keep_blocks != 0;
@@ -528,6 +542,7 @@ extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int
         C.k = -1;
       }
     }
+    lap("block growth");
     return DMRG_OK;
   } catch (const std::exception& e) {
     return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_truncate: ") + e.what());

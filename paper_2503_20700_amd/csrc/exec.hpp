@@ -11,6 +11,7 @@
 #pragma once
 #include <cstddef>
 #include <cstdint>
+#include <string>
 #include <vector>
 
 namespace dmrg {
@@ -106,6 +107,8 @@ class Executor {
   // last call to timing(true).
   virtual void timing(bool on) { (void)on; }
   virtual std::pair<double, long long> kernel_time() { return {0.0, 0}; }
+  // Host-side time spent in the executor's calls (diagnostics), one line.
+  virtual std::string host_profile() const { return std::string(); }
   // element-wise precision conversion of n values
   virtual void convert(void* dst, int dt_dst, const void* src, int dt_src, size_t n) = 0;
 };

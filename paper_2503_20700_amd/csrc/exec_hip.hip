@@ -16,6 +16,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <map>
+#include <unordered_map>
 #include <cstdio>
 #include <type_traits>
 #include <cstdlib>
@@ -611,35 +614,101 @@ void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& ter
   for (size_t i = 0; i < work.size(); ++i) items[i] = work[i].second;
 }
 
+// Wall-clock accumulator for one category of executor calls.
+struct HostTimer {
+  double s = 0.0;
+  long long n = 0;
+};
+struct Scope {
+  HostTimer& t;
+  std::chrono::steady_clock::time_point t0;
+  explicit Scope(HostTimer& x) : t(x), t0(std::chrono::steady_clock::now()) {}
+  ~Scope() {
+    t.s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    t.n++;
+  }
+};
+
 class HipExec : public Executor {
  public:
   HipExec() { HIP_OK(hipStreamCreate(&stream_)); }
   ~HipExec() override {
-    if (part_) (void)hipFree(part_);
-    if (dot_part_) (void)hipFree(dot_part_);
-    if (dot_out_) (void)hipFree(dot_out_);
+    if (stream_) (void)hipStreamSynchronize(stream_);
+    for (auto& b : size_of_) (void)hipFree(b.first);  // live and cached blocks
+    size_of_.clear();
+    free_.clear();
     for (auto& e : events_) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
     }
     if (stream_) (void)hipStreamDestroy(stream_);
   }
+  // Device memory is cached: released blocks go to a free list keyed by size
+  // and are handed out again for requests they fit (within 1/8 slack), so a
+  // sweep does not pay hipMalloc/hipFree for every operator family and task
+  // list.  All device work is ordered on the executor's one stream, so a
+  // block reused by a later call is only touched after earlier work on it.
+  // When hipMalloc fails the cache is returned to the runtime and the
+  // allocation retried once.
   void* alloc(size_t bytes) override {
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
-      (void)hipGetLastError();
-      throw std::bad_alloc();
+    Scope sc(t_alloc_);
+    const size_t s = round_size(bytes);
+    auto it = free_.lower_bound(s);
+    if (it != free_.end() && it->first <= s + s / 8) {
+      void* p = it->second;
+      cached_ -= it->first;
+      free_.erase(it);
+      return p;
     }
+    void* p = nullptr;
+    if (hipMalloc(&p, s) != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      if (hipMalloc(&p, s) != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::bad_alloc();
+      }
+    }
+    size_of_[p] = s;
     return p;
   }
   void release(void* p) override {
-    if (p) HIP_OK(hipFree(p));
+    Scope sc(t_free_);
+    if (!p) return;
+    auto it = size_of_.find(p);
+    if (it == size_of_.end()) throw std::runtime_error("executor: release of an unknown pointer");
+    free_.insert({it->second, p});
+    cached_ += it->second;
+    if (cached_ > kCacheCap) {
+      // keep the cache bounded: return the largest blocks to the runtime
+      HIP_OK(hipStreamSynchronize(stream_));
+      while (cached_ > kCacheCap / 2 && !free_.empty()) {
+        auto last = std::prev(free_.end());
+        cached_ -= last->first;
+        size_of_.erase(last->second);
+        (void)hipFree(last->second);
+        free_.erase(last);
+      }
+    }
+  }
+  // Return every cached block to the runtime.
+  void trim() {
+    if (free_.empty()) return;
+    HIP_OK(hipStreamSynchronize(stream_));
+    for (auto& f : free_) {
+      size_of_.erase(f.second);
+      (void)hipFree(f.second);
+    }
+    free_.clear();
+    cached_ = 0;
   }
   void upload(void* d, const void* s, size_t b) override {
+    Scope sc(t_up_);
     if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyHostToDevice, stream_));
     HIP_OK(hipStreamSynchronize(stream_));
   }
   void download(void* d, const void* s, size_t b) override {
+    Scope sc(t_down_);
     if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToHost, stream_));
     HIP_OK(hipStreamSynchronize(stream_));
   }
@@ -650,6 +719,7 @@ class HipExec : public Executor {
     if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, stream_));
   }
   void* prepare(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc) override {
+    Scope sc(t_prep_);
     auto* P = new Prepared();
     P->da = da;
     P->db = db;
@@ -744,7 +814,19 @@ class HipExec : public Executor {
     release(P->d_reds);
     delete P;
   }
-  void sync() override { HIP_OK(hipStreamSynchronize(stream_)); }
+  void sync() override {
+    Scope sc(t_sync_);
+    HIP_OK(hipStreamSynchronize(stream_));
+  }
+  std::string host_profile() const override {
+    char b[512];
+    std::snprintf(b, sizeof b,
+                  "alloc %.2fs/%lld free %.2fs/%lld upload %.2fs/%lld download %.2fs/%lld prepare %.2fs/%lld "
+                  "sync %.2fs/%lld",
+                  t_alloc_.s, t_alloc_.n, t_free_.s, t_free_.n, t_up_.s, t_up_.n, t_down_.s, t_down_.n, t_prep_.s,
+                  t_prep_.n, t_sync_.s, t_sync_.n);
+    return b;
+  }
   void convert(void* dst, int dd, const void* src, int ds, size_t n) override {
     if (!n) return;
     const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
@@ -802,6 +884,16 @@ class HipExec : public Executor {
 
  private:
   static unsigned grid1(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+  static size_t round_size(size_t b) {
+    if (b == 0) b = 1;
+    const size_t g = b <= ((size_t)1 << 20) ? 512 : ((size_t)2 << 20);
+    return (b + g - 1) / g * g;
+  }
+  std::multimap<size_t, void*> free_;          // cached blocks by size
+  std::unordered_map<void*, size_t> size_of_;  // every block obtained from hipMalloc
+  size_t cached_ = 0;
+  static constexpr size_t kCacheCap = (size_t)24 << 30;
+  HostTimer t_alloc_, t_free_, t_up_, t_down_, t_prep_, t_sync_;
   void* part_ = nullptr;  // partial tiles of split items, shared by all launches
   size_t part_bytes_ = 0;
   double* dot_part_ = nullptr;
