@@ -407,11 +407,14 @@ __global__ void precond_kernel(double* t, const double* r, const double* d, doub
   }
 }
 
-// ---- batched parallel Jacobi eigensolver (one work-group per matrix)
+// ---- batched two-sided Jacobi eigensolver, parallel over the whole GPU
 // Round-robin (circle) ordering over np = n rounded up to even "players":
 // in round r player 0 meets player (r % (np-1)) + 1 ... every round pairs are
 // disjoint, so all row rotations and then all column rotations of a round
-// compose to J^T A J with J the product of the round's plane rotations.
+// compose to R A R^T with R the product of the round's plane rotations.  A
+// round is two launches over all matrices of the batch: the rotation angles
+// of every pair, then the update of every 2x2 block (pair t rows, pair u
+// columns) of A and every (row, pair) of V.  np-1 rounds make one sweep.
 __device__ __forceinline__ void rr_pair(int t, int r, int np, int& p, int& q) {
   const int m = np - 1;
   if (t == 0) {
@@ -428,97 +431,141 @@ __device__ __forceinline__ void rr_pair(int t, int r, int np, int& p, int& q) {
   }
 }
 
-__global__ __launch_bounds__(256) void jacobi_kernel(double* __restrict__ Aall, double* __restrict__ Vall,
-                                                     const long long* __restrict__ offs, const int* __restrict__ sizes,
-                                                     int max_sweeps, double tol) {
-  const int n = sizes[blockIdx.x];
-  double* A = Aall + offs[blockIdx.x];
-  double* V = Vall + offs[blockIdx.x];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  __shared__ double red[256];
-  __shared__ double cs[512], sn[512];
-  __shared__ int pp[512], qq[512];
-  __shared__ double stop_flag;
-  for (long long i = tid; i < (long long)n * n; i += nt) V[i] = ((i / n) == (i % n)) ? 1.0 : 0.0;
-  if (n <= 1) return;
-  const int np = n + (n & 1);
-  const int npairs = np / 2;
-  __syncthreads();
-  // ||A||_F^2
-  double fs = 0.0;
-  for (long long i = tid; i < (long long)n * n; i += nt) fs += A[i] * A[i];
-  red[tid] = fs;
+struct JacMat {
+  long long off;        // element offset of the matrix (and of its V)
+  long long blk_base;   // first 2x2-block work index
+  long long vrow_base;  // first (row, pair) work index of V
+  int n, np, pair_base, pad;
+};
+
+__device__ __forceinline__ int jac_find(const JacMat* __restrict__ M, int nm, long long g, int which) {
+  int lo = 0, hi = nm - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const long long b = which == 0 ? (long long)M[mid].pair_base : (which == 1 ? M[mid].blk_base : M[mid].vrow_base);
+    if (b <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void jac_identity(double* __restrict__ V, const JacMat* __restrict__ M) {
+  const JacMat m = M[blockIdx.x];
+  double* v = V + m.off;
+  for (long long i = threadIdx.x; i < (long long)m.n * m.n; i += blockDim.x) v[i] = (i / m.n == i % m.n) ? 1.0 : 0.0;
+}
+
+// out[2*i] = off-diagonal sum of squares, out[2*i+1] = total, matrix i
+__global__ __launch_bounds__(256) void jac_norms(const double* __restrict__ A, const JacMat* __restrict__ M,
+                                                 double* __restrict__ out) {
+  __shared__ double r0[256], r1[256];
+  const JacMat m = M[blockIdx.x];
+  const double* a = A + m.off;
+  double off = 0.0, tot = 0.0;
+  for (long long i = threadIdx.x; i < (long long)m.n * m.n; i += blockDim.x) {
+    const double x = a[i] * a[i];
+    tot += x;
+    if (i / m.n != i % m.n) off += x;
+  }
+  r0[threadIdx.x] = off;
+  r1[threadIdx.x] = tot;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
+    if ((int)threadIdx.x < o) {
+      r0[threadIdx.x] += r0[threadIdx.x + o];
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+    }
     __syncthreads();
   }
-  const double fro2 = red[0];
-  __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0;
-    for (long long i = tid; i < (long long)n * n; i += nt)
-      if ((i / n) != (i % n)) off += A[i] * A[i];
-    red[tid] = off;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
-    if (tid == 0) stop_flag = (red[0] <= tol * tol * fro2) ? 1.0 : 0.0;
-    __syncthreads();
-    if (stop_flag != 0.0) break;
-    for (int r = 0; r < np - 1; ++r) {
-      // rotation angles for this round (pairs processed in slices of 512)
-      for (int t0 = 0; t0 < npairs; t0 += 512) {
-        const int cnt = min(512, npairs - t0);
-        for (int t = tid; t < cnt; t += nt) {
-          int p, q;
-          rr_pair(t0 + t, r, np, p, q);
-          double c = 1.0, s = 0.0;
-          if (q < n) {
-            const double apq = A[(long long)p * n + q];
-            if (apq != 0.0) {
-              const double app = A[(long long)p * n + p], aqq = A[(long long)q * n + q];
-              const double tau = (aqq - app) / (2.0 * apq);
-              const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-              c = 1.0 / sqrt(1.0 + tt * tt);
-              s = tt * c;
-            }
-          }
-          cs[t] = c;
-          sn[t] = s;
-          pp[t] = p;
-          qq[t] = (q < n) ? q : -1;
-        }
-        __syncthreads();
-        // rows p, q of A
-        for (long long i = tid; i < (long long)cnt * n; i += nt) {
-          const int t = (int)(i / n), k = (int)(i % n);
-          if (qq[t] < 0 || sn[t] == 0.0) continue;
-          const long long ip = (long long)pp[t] * n + k, iq = (long long)qq[t] * n + k;
-          const double a = A[ip], b = A[iq];
-          A[ip] = cs[t] * a - sn[t] * b;
-          A[iq] = sn[t] * a + cs[t] * b;
-        }
-        __syncthreads();
-        // columns p, q of A and of V
-        for (long long i = tid; i < (long long)cnt * n; i += nt) {
-          const int t = (int)(i / n), k = (int)(i % n);
-          if (qq[t] < 0 || sn[t] == 0.0) continue;
-          const long long ip = (long long)k * n + pp[t], iq = (long long)k * n + qq[t];
-          double a = A[ip], b = A[iq];
-          A[ip] = cs[t] * a - sn[t] * b;
-          A[iq] = sn[t] * a + cs[t] * b;
-          a = V[ip];
-          b = V[iq];
-          V[ip] = cs[t] * a - sn[t] * b;
-          V[iq] = sn[t] * a + cs[t] * b;
-        }
-        __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = r0[0];
+    out[2 * blockIdx.x + 1] = r1[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void jac_angles(const double* __restrict__ A, const JacMat* __restrict__ M, int nm,
+                                                  int npairs_total, int r, double* __restrict__ cs,
+                                                  double* __restrict__ sn, int* __restrict__ pp, int* __restrict__ qq) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= npairs_total) return;
+  const JacMat m = M[jac_find(M, nm, g, 0)];
+  const int t = g - m.pair_base;
+  double c = 1.0, s = 0.0;
+  int p = 0, q = -1;
+  if (r < m.np - 1) {
+    rr_pair(t, r, m.np, p, q);
+    if (q >= m.n) q = -1;
+    if (q >= 0) {
+      const double* a = A + m.off;
+      const double apq = a[(long long)p * m.n + q];
+      if (apq != 0.0) {
+        const double app = a[(long long)p * m.n + p], aqq = a[(long long)q * m.n + q];
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        c = 1.0 / sqrt(1.0 + tt * tt);
+        s = tt * c;
       }
     }
+  } else {
+    p = -1;  // this matrix has finished its rounds of the sweep
   }
+  cs[g] = c;
+  sn[g] = s;
+  pp[g] = p;
+  qq[g] = q;
+}
+
+// Work items [0, nblk): 2x2 blocks of A; [nblk, nblk + nvrow): (row, pair) of V.
+__global__ __launch_bounds__(256) void jac_apply(double* __restrict__ A, double* __restrict__ V,
+                                                 const JacMat* __restrict__ M, int nm, long long nblk, long long nvrow,
+                                                 const double* __restrict__ cs, const double* __restrict__ sn,
+                                                 const int* __restrict__ pp, const int* __restrict__ qq) {
+  const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (g < nblk) {
+    const JacMat m = M[jac_find(M, nm, g, 1)];
+    const int npairs = m.np >> 1;
+    const long long L = g - m.blk_base;
+    const int t = (int)(L / npairs), u = (int)(L % npairs);
+    const int it = m.pair_base + t, iu = m.pair_base + u;
+    const int pt = pp[it], qt = qq[it], pu = pp[iu], qu = qq[iu];
+    if (pt < 0) return;  // matrix idle in this round
+    if (sn[it] == 0.0 && sn[iu] == 0.0) return;
+    double* a = A + m.off;
+    const long long n = m.n;
+    const double ct = cs[it], st = sn[it], cu = cs[iu], su = sn[iu];
+    // block rows {pt, qt}, cols {pu, qu}; missing indices (q = -1) are absent
+    double b00 = a[pt * n + pu];
+    double b01 = qu >= 0 ? a[pt * n + qu] : 0.0;
+    double b10 = qt >= 0 ? a[qt * n + pu] : 0.0;
+    double b11 = (qt >= 0 && qu >= 0) ? a[qt * n + qu] : 0.0;
+    // rows: p' = c p - s q, q' = s p + c q
+    double r00 = ct * b00 - st * b10, r01 = ct * b01 - st * b11;
+    double r10 = st * b00 + ct * b10, r11 = st * b01 + ct * b11;
+    // columns likewise
+    b00 = cu * r00 - su * r01;
+    b01 = su * r00 + cu * r01;
+    b10 = cu * r10 - su * r11;
+    b11 = su * r10 + cu * r11;
+    a[pt * n + pu] = b00;
+    if (qu >= 0) a[pt * n + qu] = b01;
+    if (qt >= 0) a[qt * n + pu] = b10;
+    if (qt >= 0 && qu >= 0) a[qt * n + qu] = b11;
+    return;
+  }
+  const long long h = g - nblk;
+  if (h >= nvrow) return;
+  const JacMat m = M[jac_find(M, nm, h, 2)];
+  const int npairs = m.np >> 1;
+  const long long L = h - m.vrow_base;
+  const long long i = L / npairs;
+  const int iu = m.pair_base + (int)(L % npairs);
+  const int pu = pp[iu], qu = qq[iu];
+  if (pu < 0 || qu < 0 || sn[iu] == 0.0) return;
+  double* v = V + m.off + i * m.n;
+  const double cu = cs[iu], su = sn[iu];
+  const double x = v[pu], y = v[qu];
+  v[pu] = cu * x - su * y;
+  v[qu] = su * x + cu * y;
 }
 
 struct Prepared {
@@ -869,16 +916,79 @@ class HipExec : public Executor {
   void sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes, int max_sweeps,
                double tol) override {
     if (offs.empty()) return;
-    long long* d_off = (long long*)alloc(offs.size() * sizeof(long long));
-    int* d_sz = (int*)alloc(sizes.size() * sizeof(int));
-    upload(d_off, offs.data(), offs.size() * sizeof(long long));
-    upload(d_sz, sizes.data(), sizes.size() * sizeof(int));
-    hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)offs.size()), dim3(256), 0, stream_, A, V, d_off, d_sz,
-                       max_sweeps, tol);
+    const int nall = (int)offs.size();
+    // per-matrix descriptors of a list of matrices (bases for the work indices)
+    auto describe = [&](const std::vector<int>& ids, std::vector<JacMat>& M, long long& npair, long long& nblk,
+                        long long& nvrow, int& maxnp) {
+      M.clear();
+      npair = nblk = nvrow = 0;
+      maxnp = 0;
+      for (int i : ids) {
+        JacMat m{};
+        m.off = offs[i];
+        m.n = sizes[i];
+        m.np = m.n + (m.n & 1);
+        m.pair_base = (int)npair;
+        m.blk_base = nblk;
+        m.vrow_base = nvrow;
+        const long long h = m.np / 2;
+        npair += h;
+        nblk += h * h;
+        nvrow += (long long)m.n * h;
+        maxnp = std::max(maxnp, m.np);
+        M.push_back(m);
+      }
+    };
+    std::vector<int> all(nall);
+    for (int i = 0; i < nall; ++i) all[i] = i;
+    std::vector<JacMat> M;
+    long long npair, nblk, nvrow;
+    int maxnp;
+    describe(all, M, npair, nblk, nvrow, maxnp);
+    JacMat* dM = (JacMat*)alloc(M.size() * sizeof(JacMat));
+    double* dnorm = (double*)alloc(2 * (size_t)nall * sizeof(double));
+    double* dcs = (double*)alloc((size_t)npair * sizeof(double));
+    double* dsn = (double*)alloc((size_t)npair * sizeof(double));
+    int* dpp = (int*)alloc((size_t)npair * sizeof(int));
+    int* dqq = (int*)alloc((size_t)npair * sizeof(int));
+    upload(dM, M.data(), M.size() * sizeof(JacMat));
+    hipLaunchKernelGGL(jac_identity, dim3(nall), dim3(256), 0, stream_, V, dM);
+    hipLaunchKernelGGL(jac_norms, dim3(nall), dim3(256), 0, stream_, A, dM, dnorm);
     HIP_OK(hipGetLastError());
-    sync();
-    release(d_off);
-    release(d_sz);
+    std::vector<double> nrm(2 * (size_t)nall);
+    download(nrm.data(), dnorm, nrm.size() * sizeof(double));
+    std::vector<double> fro2(nall);
+    std::vector<int> active;
+    for (int i = 0; i < nall; ++i) {
+      fro2[i] = nrm[2 * i + 1];
+      if (sizes[i] > 1 && nrm[2 * i] > tol * tol * fro2[i]) active.push_back(i);
+    }
+    for (int sweep = 0; sweep < max_sweeps && !active.empty(); ++sweep) {
+      describe(active, M, npair, nblk, nvrow, maxnp);
+      const int nm = (int)M.size();
+      upload(dM, M.data(), M.size() * sizeof(JacMat));
+      const unsigned ga = (unsigned)((npair + 255) / 256);
+      const unsigned gb = (unsigned)((nblk + nvrow + 255) / 256);
+      for (int r = 0; r < maxnp - 1; ++r) {
+        hipLaunchKernelGGL(jac_angles, dim3(ga), dim3(256), 0, stream_, A, dM, nm, (int)npair, r, dcs, dsn, dpp, dqq);
+        hipLaunchKernelGGL(jac_apply, dim3(gb), dim3(256), 0, stream_, A, V, dM, nm, nblk, nvrow, dcs, dsn, dpp,
+                           dqq);
+      }
+      HIP_OK(hipGetLastError());
+      hipLaunchKernelGGL(jac_norms, dim3(nm), dim3(256), 0, stream_, A, dM, dnorm);
+      HIP_OK(hipGetLastError());
+      download(nrm.data(), dnorm, 2 * (size_t)nm * sizeof(double));
+      std::vector<int> still;
+      for (int j = 0; j < nm; ++j)
+        if (nrm[2 * j] > tol * tol * fro2[active[j]]) still.push_back(active[j]);
+      active.swap(still);
+    }
+    release(dM);
+    release(dnorm);
+    release(dcs);
+    release(dsn);
+    release(dpp);
+    release(dqq);
   }
   hipStream_t stream() const { return stream_; }
 

@@ -115,3 +115,34 @@ def test_block_growth_after_truncation_matches_oracle(direction, case):
     y, _ = dm.hpsi(p2)
     ref = he.apply(p2)
     assert np.abs(y - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_cut_spectrum_at_cas32_d1024_matches_numpy():
+    # Full size of the CAS(32,32) D=1024 workload: reduced density matrices of
+    # the enlarged left block are up to ~300 wide.  Their spectra from the
+    # GPU Jacobi solver equal numpy's eigvalsh of rho_a = sum_c psi_ac psi_ac^T
+    # built on the host from the psi layout.
+    from paper_2503_20700_amd.binding import DMRG
+    from synth.integrals import huckel_chain
+    h, g, _ = huckel_chain(32, 1, naux=96)
+    mps = random_mps(32, 32, 0, 1024, k=15, seed=1)
+    psi, lay = random_psi(mps, seed=2)
+    psi /= np.linalg.norm(psi)
+    dm = DMRG(h, g, 32, 0)
+    bs, cnt = mps.bond_table()
+    dm.set_mps(15, bs, cnt, mps.site_blocks_flat())
+    err, kept = dm.truncate(psi, 10 ** 6, 0.0, 1)
+    vals, spins = dm.cut_spectrum()
+    ref = []
+    by_a = {}
+    for b in lay:
+        m = psi[b["offset"]:b["offset"] + b["nrows"] * b["ncols"]].reshape(b["nrows"], b["ncols"])
+        by_a.setdefault(b["a"], []).append(m)
+    for a, ms in by_a.items():
+        rho = sum(m @ m.T for m in ms)
+        ref.extend(np.linalg.eigvalsh(rho))
+    ref = np.sort(np.clip(ref, 0.0, None))[::-1]
+    w = np.sort(vals ** 2)[::-1]
+    print(f"[cut spectrum] sectors={len(by_a)} max dim={max(len(ms[0]) for ms in by_a.values())} n={len(w)}", flush=True)
+    assert abs(w.sum() - 1.0) < 1e-12
+    assert np.abs(w - ref[:len(w)]).max() < 1e-13
