@@ -158,7 +158,10 @@ int dmrg_kernel_timing(dmrg_ctx *c, int mode, double *ms, long long *launches);
  * grouped MFMA kernel the hot path uses (host FP64 buffers; A is m x k or,
  * with trans_a, k x m row-major; B is k x n or n x k).  ident_a / ident_b
  * replace the operand by the identity (k must then equal m / n).  prec as in
- * dmrg_hpsi: operands are rounded to it, accumulation is FP64 (FP64) or FP32. */
+ * dmrg_hpsi: operands are rounded to it, accumulation is FP64 (FP64) or FP32.
+ * Bit 1 of trans_a / trans_b (value 2) stores that operand with its rows
+ * padded to a multiple of 8 elements (padding filled with NaN) and marks it
+ * padded, which selects the kernel's 16-byte vector staging path. */
 int dmrg_gemm_selftest(int m, int n, int k, const double *A, int trans_a, int ident_a, const double *B,
                        int trans_b, int ident_b, double alpha, double beta, double *C, int prec);
 

@@ -84,8 +84,10 @@ def exported_symbols():
 
 
 def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ident_b=False, alpha=1.0, beta=0.0,
-                  prec=FP64, lib=None):
-    """C = beta*C + alpha op(A) op(B) through the library's grouped MFMA kernel."""
+                  prec=FP64, pad_a=False, pad_b=False, lib=None):
+    """C = beta*C + alpha op(A) op(B) through the library's grouped MFMA kernel.
+    pad_a / pad_b store that operand with NaN-padded rows (multiple of 8) and
+    select the kernel's vector staging path."""
     lib = load(lib)
     if ident_a:
         B = np.ascontiguousarray(B, dtype=np.float64)
@@ -101,8 +103,9 @@ def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ide
             n = B.shape[0] if trans_b else B.shape[1]
     C = np.zeros((m, n)) if C is None else np.ascontiguousarray(C, dtype=np.float64).copy()
     dummy = np.zeros(1)
-    rc = lib.dmrg_gemm_selftest(m, n, k, _dp(dummy if ident_a else A), int(trans_a), int(ident_a),
-                                _dp(dummy if ident_b else B), int(trans_b), int(ident_b), alpha, beta, _dp(C), prec)
+    rc = lib.dmrg_gemm_selftest(m, n, k, _dp(dummy if ident_a else A), int(trans_a) | (2 if pad_a else 0),
+                                int(ident_a), _dp(dummy if ident_b else B), int(trans_b) | (2 if pad_b else 0),
+                                int(ident_b), alpha, beta, _dp(C), prec)
     if rc != 0:
         raise DMRGError(rc, lib.dmrg_last_error().decode())
     return C

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -284,14 +285,32 @@ extern "C" int dmrg_gemm_selftest(int m, int n, int k, const double* A, int ta, 
       ex->release(p64);
       return p;
     };
-    void* dA = ia ? nullptr : put(A, (size_t)m * k, dt);
-    void* dB = ib ? nullptr : put(B, (size_t)k * n, dt);
+    // bit 1 of ta / tb: store the operand with rows padded to a multiple of 8
+    // elements, padding filled with NaN, and flag it as padded
+    const bool pa = (ta & 2) != 0, pb = (tb & 2) != 0;
+    ta &= 1;
+    tb &= 1;
+    auto padded = [](const double* h, int rows, int cols, int ld) {
+      std::vector<double> v((size_t)rows * ld, std::numeric_limits<double>::quiet_NaN());
+      for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c) v[(size_t)r * ld + c] = h[(size_t)r * cols + c];
+      return v;
+    };
+    const int rA = ta ? k : m, cA = ta ? m : k, rB = tb ? n : k, cB = tb ? k : n;
+    const int ldA = pa ? (cA + 7) / 8 * 8 : cA, ldB = pb ? (cB + 7) / 8 * 8 : cB;
+    std::vector<double> hA, hB;
+    if (!ia) hA = pa ? padded(A, rA, cA, ldA) : std::vector<double>(A, A + (size_t)m * k);
+    if (!ib) hB = pb ? padded(B, rB, cB, ldB) : std::vector<double>(B, B + (size_t)k * n);
+    void* dA = ia ? nullptr : put(hA.data(), hA.size(), dt);
+    void* dB = ib ? nullptr : put(hB.data(), hB.size(), dt);
     std::vector<double> cb((size_t)m * n);
     for (size_t i = 0; i < cb.size(); ++i) cb[i] = beta * C[i];
     void* dC = put(cb.data(), cb.size(), dc);
     RawJob j{dC, m, n, n, 1, 0, 0, 1};
-    RawTerm t{dA, dB, ta ? m : k, tb ? k : n, k, (ta ? TF_TRANS_A : 0) | (tb ? TF_TRANS_B : 0) |
-                                                 (ia ? TF_IDENT_A : 0) | (ib ? TF_IDENT_B : 0), alpha};
+    RawTerm t{dA, dB, ldA, ldB, k,
+              (ta ? TF_TRANS_A : 0) | (tb ? TF_TRANS_B : 0) | (ia ? TF_IDENT_A : 0) | (ib ? TF_IDENT_B : 0) |
+                  (pa ? TF_PAD_A : 0) | (pb ? TF_PAD_B : 0),
+              alpha};
     void* h = ex->prepare({j}, {t}, dt, dt, dc);
     ex->run(h);
     ex->sync();

@@ -19,7 +19,9 @@ namespace dmrg {
 enum DType : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_FP8 = 3 };
 inline size_t dtype_size(int dt) { return dt == DT_F64 ? 8 : dt == DT_F32 ? 4 : dt == DT_BF16 ? 2 : 1; }
 
-enum TermFlags : int { TF_TRANS_A = 1, TF_TRANS_B = 2, TF_IDENT_A = 4, TF_IDENT_B = 8 };
+// TF_PAD_A / TF_PAD_B: the operand's rows are padded to a multiple of 8
+// elements (readable up to the padded length) and start 16-byte aligned.
+enum TermFlags : int { TF_TRANS_A = 1, TF_TRANS_B = 2, TF_IDENT_A = 4, TF_IDENT_B = 8, TF_PAD_A = 16, TF_PAD_B = 32 };
 
 // Pointers are element offsets into named buffers, resolved per precision.
 struct BufRef {
@@ -109,6 +111,8 @@ class Executor {
   virtual std::pair<double, long long> kernel_time() { return {0.0, 0}; }
   // Host-side time spent in the executor's calls (diagnostics), one line.
   virtual std::string host_profile() const { return std::string(); }
+  // dst[i] = idx[i] >= 0 ? src[idx[i]] : 0 for i < n, converted to dt_dst
+  virtual void pack(void* dst, int dt_dst, const double* src, const int* idx, size_t n) = 0;
   // element-wise precision conversion of n values
   virtual void convert(void* dst, int dt_dst, const void* src, int dt_src, size_t n) = 0;
 };

@@ -103,50 +103,331 @@ struct RedItem {
   int job, ti, tj, slot0, nslot, pad;
 };
 
-// MODE: DT_F64 / DT_F32 / DT_BF16 arithmetic; DA/DB/DC storage types.
-// The K loop is software-pipelined: the global loads of the next K slab
-// (which may belong to the next product) are issued into registers before the
-// MFMAs of the current slab, and LDS is double-buffered, so each K step has a
-// single barrier.
-template <int MODE, int DA, int DB, int DC>
+// MODE: DT_F64 / DT_F32 / DT_BF16 arithmetic; A and B are stored in the
+// arithmetic type, C in DC.
+//
+// The K loop runs over the flattened (product, K slab) sequence of the item
+// and is software-pipelined: the global loads of the next slab (which may
+// belong to the next product) are issued into registers before the MFMAs of
+// the current slab, and LDS is double-buffered, so each K step has a single
+// barrier.  In the FP32/BF16 paths each product is accumulated on its own and
+// added to the tile with its weight alpha (in FP32) when its last slab is
+// done, so operands are staged unscaled (BF16 bits are copied unchanged and
+// the weight is not rounded into the operand); the FP64 path scales A by
+// alpha while staging it.
+//
+// Operands flagged TF_PAD_A / TF_PAD_B (and 16-byte aligned, with a row
+// stride that keeps every row 16-byte aligned) have rows padded to a multiple
+// of 8 elements; they are staged with 16-byte vector loads along their
+// contiguous dimension, masking the elements past the logical extent.  Other
+// operands are staged element by element.
+enum { LD_SCALAR = 0, LD_VEC_K = 1, LD_VEC_MN = 2 };
+
+// Zero the elements of a 16-byte vector of ES-byte elements from index nvalid on.
+template <int ES>
+__device__ __forceinline__ uint4 keep_first(uint4 x, int nvalid) {
+  unsigned w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    unsigned m;
+    if constexpr (ES == 2) m = (2 * d < nvalid ? 0x0000ffffu : 0u) | (2 * d + 1 < nvalid ? 0xffff0000u : 0u);
+    else if constexpr (ES == 4) m = d < nvalid ? 0xffffffffu : 0u;
+    else m = (d / 2) < nvalid ? 0xffffffffu : 0u;
+    w[d] &= m;
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+template <int MODE, int DC, int KT>
 __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms,
                                                    const WorkItem* __restrict__ items, void* __restrict__ part) {
   using acc_t = typename std::conditional<MODE == DT_F64, d4, f4>::type;
   using sc_t = typename std::conditional<MODE == DT_F64, double, float>::type;
-  using ra_t = typename raw_of<DA>::T;
-  using rb_t = typename raw_of<DB>::T;
-  constexpr int KT = (MODE == DT_BF16) ? 32 : 16;
-  // F64/F32: LDS k-major [KT][TM+1]; BF16: row-major [TM][KT+8] of bf16 bits
-  constexpr int LDS_A = (MODE == DT_BF16) ? TM * (KT + 8) * 2 : KT * (TM + 1) * (MODE == DT_F64 ? 8 : 4);
-  constexpr int PER = TM * KT / 256;
+  using el_t = typename raw_of<MODE>::T;
+  static_assert(MODE == DT_BF16 ? (KT % 32 == 0) : (KT == 16), "K slab: multiple of 32 (BF16) or 16");
+  constexpr int VW = 16 / (int)sizeof(el_t);  // elements per 16-byte vector
+  constexpr int PER = TM * KT / 256;           // elements of each operand per thread and slab
+  constexpr int NV = PER / VW;                 // 16-byte vectors per thread and slab
+  static_assert(NV * VW == PER && NV >= 1, "slab must split into whole vectors");
+  // BF16: LDS row-major [TM][KT+8] (k contiguous, MFMA operand layout);
+  // F32/F64: LDS k-major [KT][TM+1]
+  constexpr int LDA_S = (MODE == DT_BF16) ? KT + 8 : TM + 1;
+  constexpr int LDS_A = (MODE == DT_BF16) ? TM * (KT + 8) * 2 : KT * (TM + 1) * (int)sizeof(el_t);
   __shared__ __attribute__((aligned(16))) unsigned char smem[4 * LDS_A];
 
   const int tid = threadIdx.x;
-  const WorkItem W = items[blockIdx.x];
-  const RawJob J = jobs[W.job];
-  const int m0 = W.ti * TM, n0 = W.tj * TN;
+  WorkItem W;       // the work item of this work-group
+  RawJob J;
+  int m0 = 0, n0 = 0;
+  int lmm = 0, lnn = 0, lm0 = 0, ln0 = 0;  // extents and origin of the tile being loaded
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lg = lane >> 4;
 
-  acc_t acc[2][2];
+  acc_t acc[2][2], accp[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = accp[a][b][v] = 0;
 
   // ---- identity products: C += alpha * (the other operand), read at this
   // lane's accumulator positions.
-  for (int t = W.tbeg; t < W.tend; ++t) {
-    const int fl = terms[t].flags;
-    if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+  auto identity_pass = [&]() {
+    for (int t = W.tbeg; t < W.tend; ++t) {
+      const int fl = terms[t].flags;
+      if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+      const RawTerm T = terms[t];
+      const bool ia = fl & TF_IDENT_A;
+      const void* P = ia ? T.B : T.A;
+      const long long ld = ia ? T.ldb : T.lda;
+      const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = m0 + wm + a * 16 + acc_row<MODE>(lg, v);
+            const int col = n0 + wn + b * 16 + lr;
+            if (row < J.m && col < J.n) {
+              const long long idx = tr ? (long long)col * ld + row : (long long)row * ld + col;
+              acc[a][b][v] += (sc_t)(T.alpha * ldv<MODE>(P, idx));
+            }
+          }
+    }
+  };
+
+  auto next_dense = [&](int t, int tend) {
+    while (t < tend && (terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) ++t;
+    return t;
+  };
+  union Regs {
+    uint4 v[NV];
+    el_t e[PER];
+  };
+  Regs ra, rb;
+  int amode = LD_SCALAR, bmode = LD_SCALAR, rflags = 0;
+  constexpr bool kScaleA = (MODE == DT_F64);  // weight applied to A while staging
+  sc_t ralpha = 1;
+
+  auto vec_ok = [](const void* p, long long ld) {
+    return (((unsigned long long)p & 15ull) == 0) && (((ld * (long long)sizeof(el_t)) & 15ll) == 0);
+  };
+  // Fill the registers with slab k0 of product t.
+  auto load = [&](int t, int k0) {
     const RawTerm T = terms[t];
-    const bool ia = fl & TF_IDENT_A;
-    const void* P = ia ? T.B : T.A;
-    const long long ld = ia ? T.ldb : T.lda;
-    const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+    const int K = T.k;
+    const bool ta = T.flags & TF_TRANS_A, tb = T.flags & TF_TRANS_B;
+    rflags = T.flags;
+    if constexpr (kScaleA) ralpha = (sc_t)T.alpha;
+    const el_t* A = (const el_t*)T.A;
+    const el_t* B = (const el_t*)T.B;
+    amode = ((T.flags & TF_PAD_A) && vec_ok(T.A, T.lda)) ? (ta ? LD_VEC_MN : LD_VEC_K) : LD_SCALAR;
+    bmode = ((T.flags & TF_PAD_B) && vec_ok(T.B, T.ldb)) ? (tb ? LD_VEC_K : LD_VEC_MN) : LD_SCALAR;
+    // ---- A (TM x KT)
+    if (amode == LD_VEC_K) {  // rows i, vectors along k
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int gv = tid + 256 * v;
+        const int i = gv / (KT / VW), kv = (gv % (KT / VW)) * VW;
+        const int gi = lm0 + i, gk = k0 + kv;
+        ra.v[v] = make_uint4(0, 0, 0, 0);
+        if (gi < lmm && gk < K) {
+          ra.v[v] = *(const uint4*)(A + (long long)gi * T.lda + gk);
+          if (K - gk < VW) ra.v[v] = keep_first<sizeof(el_t)>(ra.v[v], K - gk);
+        }
+      }
+    } else if (amode == LD_VEC_MN) {  // rows k, vectors along i
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int gv = tid + 256 * v;
+        const int kk = gv / (TM / VW), iv = (gv % (TM / VW)) * VW;
+        const int gi = lm0 + iv, gk = k0 + kk;
+        ra.v[v] = make_uint4(0, 0, 0, 0);
+        if (gi < lmm && gk < K) {
+          ra.v[v] = *(const uint4*)(A + (long long)gk * T.lda + gi);
+          if (lmm - gi < VW) ra.v[v] = keep_first<sizeof(el_t)>(ra.v[v], lmm - gi);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int idx = tid + 256 * r;
+        int i, kk;
+        if (!ta) { i = idx / KT; kk = idx % KT; } else { kk = idx / TM; i = idx % TM; }
+        const int gi = lm0 + i, gk = k0 + kk;
+        ra.e[r] = (el_t)0;
+        if (gi < lmm && gk < K) ra.e[r] = A[ta ? (long long)gk * T.lda + gi : (long long)gi * T.lda + gk];
+      }
+    }
+    // ---- B (KT x TN)
+    if (bmode == LD_VEC_K) {  // stored transposed: rows j, vectors along k
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int gv = tid + 256 * v;
+        const int j = gv / (KT / VW), kv = (gv % (KT / VW)) * VW;
+        const int gj = ln0 + j, gk = k0 + kv;
+        rb.v[v] = make_uint4(0, 0, 0, 0);
+        if (gj < lnn && gk < K) {
+          rb.v[v] = *(const uint4*)(B + (long long)gj * T.ldb + gk);
+          if (K - gk < VW) rb.v[v] = keep_first<sizeof(el_t)>(rb.v[v], K - gk);
+        }
+      }
+    } else if (bmode == LD_VEC_MN) {  // rows k, vectors along j
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int gv = tid + 256 * v;
+        const int kk = gv / (TN / VW), jv = (gv % (TN / VW)) * VW;
+        const int gj = ln0 + jv, gk = k0 + kk;
+        rb.v[v] = make_uint4(0, 0, 0, 0);
+        if (gj < lnn && gk < K) {
+          rb.v[v] = *(const uint4*)(B + (long long)gk * T.ldb + gj);
+          if (lnn - gj < VW) rb.v[v] = keep_first<sizeof(el_t)>(rb.v[v], lnn - gj);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int idx = tid + 256 * r;
+        int j, kk;
+        if (!tb) { kk = idx / TN; j = idx % TN; } else { j = idx / KT; kk = idx % KT; }
+        const int gj = ln0 + j, gk = k0 + kk;
+        rb.e[r] = (el_t)0;
+        if (gj < lnn && gk < K) rb.e[r] = B[tb ? (long long)gj * T.ldb + gk : (long long)gk * T.ldb + gj];
+      }
+    }
+  };
+  // Element (i, k) of the A slab / (k, j) of the B slab into LDS.
+  auto putA = [&](el_t* sA, int i, int kk, el_t x) {
+    if constexpr (MODE == DT_BF16) sA[i * LDA_S + kk] = x;
+    else if constexpr (kScaleA) sA[kk * LDA_S + i] = x * ralpha;
+    else sA[kk * LDA_S + i] = x;
+  };
+  auto putB = [&](el_t* sB, int j, int kk, el_t x) {
+    if constexpr (MODE == DT_BF16) sB[j * LDA_S + kk] = x;
+    else sB[kk * LDA_S + j] = x;
+  };
+  auto store = [&](unsigned char* sAb, unsigned char* sBb) {
+    el_t* sA = (el_t*)sAb;
+    el_t* sB = (el_t*)sBb;
+    if (amode == LD_VEC_K) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int gv = tid + 256 * v;
+        const int i = gv / (KT / VW), kv = (gv % (KT / VW)) * VW;
+        if constexpr (MODE == DT_BF16) {
+          *(uint4*)(sA + i * LDA_S + kv) = ra.v[v];
+        } else {
+#pragma unroll
+          for (int q = 0; q < VW; ++q) putA(sA, i, kv + q, ra.e[v * VW + q]);
+        }
+      }
+    } else if (amode == LD_VEC_MN) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int gv = tid + 256 * v;
+        const int kk = gv / (TM / VW), iv = (gv % (TM / VW)) * VW;
+#pragma unroll
+        for (int q = 0; q < VW; ++q) putA(sA, iv + q, kk, ra.e[v * VW + q]);
+      }
+    } else {
+      const bool ta = rflags & TF_TRANS_A;
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int idx = tid + 256 * r;
+        int i, kk;
+        if (!ta) { i = idx / KT; kk = idx % KT; } else { kk = idx / TM; i = idx % TM; }
+        putA(sA, i, kk, ra.e[r]);
+      }
+    }
+    // B: the LDS layout of B^T equals that of A (rows j)
+    if (bmode == LD_VEC_K) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int gv = tid + 256 * v;
+        const int j = gv / (KT / VW), kv = (gv % (KT / VW)) * VW;
+        if constexpr (MODE == DT_BF16) {
+          *(uint4*)(sB + j * LDA_S + kv) = rb.v[v];
+        } else {
+#pragma unroll
+          for (int q = 0; q < VW; ++q) putB(sB, j, kv + q, rb.e[v * VW + q]);
+        }
+      }
+    } else if (bmode == LD_VEC_MN) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int gv = tid + 256 * v;
+        const int kk = gv / (TN / VW), jv = (gv % (TN / VW)) * VW;
+#pragma unroll
+        for (int q = 0; q < VW; ++q) putB(sB, jv + q, kk, rb.e[v * VW + q]);
+      }
+    } else {
+      const bool tb = rflags & TF_TRANS_B;
+#pragma unroll
+      for (int r = 0; r < PER; ++r) {
+        const int idx = tid + 256 * r;
+        int j, kk;
+        if (!tb) { kk = idx / TN; j = idx % TN; } else { j = idx / KT; kk = idx % KT; }
+        putB(sB, j, kk, rb.e[r]);
+      }
+    }
+  };
+  auto compute = [&](const unsigned char* sA, const unsigned char* sB) {
+    if constexpr (MODE == DT_BF16) {
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += 32) {
+        bf8 av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          av[a] = *(const bf8*)&((const u16*)sA)[(wm + a * 16 + lr) * LDA_S + kk + 8 * lg];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          bv[b] = *(const bf8*)&((const u16*)sB)[(wn + b * 16 + lr) * LDA_S + kk + 8 * lg];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            accp[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], accp[a][b], 0, 0, 0);
+      }
+    } else {
+      const sc_t* A_ = (const sc_t*)sA;
+      const sc_t* B_ = (const sc_t*)sB;
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += 4) {
+        const sc_t a0 = A_[(kk + lg) * LDA_S + wm + lr];
+        const sc_t a1 = A_[(kk + lg) * LDA_S + wm + 16 + lr];
+        const sc_t b0 = B_[(kk + lg) * LDA_S + wn + lr];
+        const sc_t b1 = B_[(kk + lg) * LDA_S + wn + 16 + lr];
+        if constexpr (MODE == DT_F64) {
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        } else {
+          accp[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, accp[0][0], 0, 0, 0);
+          accp[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, accp[0][1], 0, 0, 0);
+          accp[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, accp[1][0], 0, 0, 0);
+          accp[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, accp[1][1], 0, 0, 0);
+        }
+      }
+    }
+  };
+
+  // ---- write back the finished item (C, or its partial slot)
+  auto write_back = [&]() {
+    if (W.slot >= 0) {
+      sc_t* P = (sc_t*)part + (long long)W.slot * (TM * TN);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            P[(wm + a * 16 + acc_row<MODE>(lg, v)) * TN + wn + b * 16 + lr] = acc[a][b][v];
+      return;
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -156,161 +437,70 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
           const int row = m0 + wm + a * 16 + acc_row<MODE>(lg, v);
           const int col = n0 + wn + b * 16 + lr;
           if (row < J.m && col < J.n) {
-            const long long idx = tr ? (long long)col * ld + row : (long long)row * ld + col;
-            const double x = ia ? ldv<DB>(P, idx) : ldv<DA>(P, idx);
-            acc[a][b][v] += (sc_t)(T.alpha * x);
+            const long long o = (long long)row * J.ldc + col;
+            if (J.accumulate) {
+              if constexpr (DC == DT_F64) ((double*)J.C)[o] += (double)acc[a][b][v];
+              else stv<DC>(J.C, o, ldv<DC>(J.C, o) + (double)acc[a][b][v]);
+            } else {
+              stv<DC>(J.C, o, acc[a][b][v]);
+            }
           }
         }
-  }
 
-  // ---- dense products, pipelined over the flattened (product, k0) sequence
-  auto next_dense = [&](int t) {
-    while (t < W.tend && (terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) ++t;
-    return t;
   };
-  ra_t ra[PER];
-  rb_t rb[PER];
-  sc_t ralpha = 0;
-  auto load = [&](int t, int k0) {
-    const RawTerm T = terms[t];
-    const int K = T.k;
-    const bool ta = T.flags & TF_TRANS_A, tb = T.flags & TF_TRANS_B;
-    ralpha = (sc_t)T.alpha;
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int idx = tid + 256 * r;
-      int i, kk;
-      if (!ta) { i = idx / KT; kk = idx % KT; } else { kk = idx / TM; i = idx % TM; }
-      const int gi = m0 + i, gk = k0 + kk;
-      ra[r] = 0;
-      if (gi < J.m && gk < K) ra[r] = ((const ra_t*)T.A)[ta ? (long long)gk * T.lda + gi : (long long)gi * T.lda + gk];
-    }
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int idx = tid + 256 * r;
-      int j, kk;
-      if (!tb) { kk = idx / TN; j = idx % TN; } else { j = idx / KT; kk = idx % KT; }
-      const int gj = n0 + j, gk = k0 + kk;
-      rb[r] = 0;
-      if (gj < J.n && gk < K) rb[r] = ((const rb_t*)T.B)[tb ? (long long)gj * T.ldb + gk : (long long)gk * T.ldb + gj];
-    }
+  auto set_load_tile = [&](const WorkItem& w, const RawJob& j) {
+    lmm = j.m;
+    lnn = j.n;
+    lm0 = w.ti * TM;
+    ln0 = w.tj * TN;
   };
-  // The LDS position of register r depends on the product's transposition
-  // flags, which are kept with the registers.
-  int rflags = 0;
-  auto store = [&](unsigned char* sA, unsigned char* sB) {
-    const bool ta = rflags & TF_TRANS_A, tb = rflags & TF_TRANS_B;
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int idx = tid + 256 * r;
-      int i, kk;
-      if (!ta) { i = idx / KT; kk = idx % KT; } else { kk = idx / TM; i = idx % TM; }
-      const sc_t v = raw_to<DA, sc_t>(ra[r]) * ralpha;
-      if constexpr (MODE == DT_BF16) ((u16*)sA)[i * (KT + 8) + kk] = f2bf(v);
-      else ((sc_t*)sA)[kk * (TM + 1) + i] = v;
+  {
+    W = items[blockIdx.x];
+    J = jobs[W.job];
+    m0 = W.ti * TM;
+    n0 = W.tj * TN;
+    int t = next_dense(W.tbeg, W.tend), k0 = 0;
+    if (t < W.tend) {
+      set_load_tile(W, J);
+      load(t, 0);
     }
-#pragma unroll
-    for (int r = 0; r < PER; ++r) {
-      const int idx = tid + 256 * r;
-      int j, kk;
-      if (!tb) { kk = idx / TN; j = idx % TN; } else { j = idx / KT; kk = idx % KT; }
-      const sc_t v = raw_to<DB, sc_t>(rb[r]);
-      if constexpr (MODE == DT_BF16) ((u16*)sB)[j * (KT + 8) + kk] = f2bf(v);
-      else ((sc_t*)sB)[kk * (TN + 1) + j] = v;
-    }
-  };
-  auto compute = [&](const unsigned char* sA, const unsigned char* sB) {
-    if constexpr (MODE == DT_BF16) {
-      bf8 av[2], bv[2];
-#pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = *(const bf8*)&((const u16*)sA)[(wm + a * 16 + lr) * (KT + 8) + 8 * lg];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = *(const bf8*)&((const u16*)sB)[(wn + b * 16 + lr) * (KT + 8) + 8 * lg];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
-    } else {
-      const sc_t* A_ = (const sc_t*)sA;
-      const sc_t* B_ = (const sc_t*)sB;
-#pragma unroll
-      for (int kk = 0; kk < KT; kk += 4) {
-        const sc_t a0 = A_[(kk + lg) * (TM + 1) + wm + lr];
-        const sc_t a1 = A_[(kk + lg) * (TM + 1) + wm + 16 + lr];
-        const sc_t b0 = B_[(kk + lg) * (TN + 1) + wn + lr];
-        const sc_t b1 = B_[(kk + lg) * (TN + 1) + wn + 16 + lr];
-        if constexpr (MODE == DT_F64) {
-          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        } else {
-          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
-        }
+    identity_pass();
+    int buf = 0;
+    while (t < W.tend) {
+      unsigned char* sA = smem + buf * 2 * LDS_A;
+      unsigned char* sB = sA + LDS_A;
+      store(sA, sB);
+      __syncthreads();
+      const RawTerm& Tc = terms[t];
+      const int Kc = Tc.k;
+      const sc_t alpha = (sc_t)Tc.alpha;
+      int t2 = t, k2 = k0 + KT;
+      const bool last = k2 >= Kc;
+      if (last) {
+        t2 = next_dense(t + 1, W.tend);
+        k2 = 0;
       }
-    }
-  };
-
-  int t = next_dense(W.tbeg), k0 = 0;
-  if (t < W.tend) {
-    load(t, k0);
-    rflags = terms[t].flags;
-  }
-  int buf = 0;
-  while (t < W.tend) {
-    unsigned char* sA = smem + buf * 2 * LDS_A;
-    unsigned char* sB = sA + LDS_A;
-    store(sA, sB);
-    __syncthreads();
-    int t2 = t, k2 = k0 + KT;
-    if (k2 >= terms[t].k) {
-      t2 = next_dense(t + 1);
-      k2 = 0;
-    }
-    if (t2 < W.tend) {
-      load(t2, k2);
-      rflags = terms[t2].flags;
-    }
-    compute(sA, sB);
-    buf ^= 1;
-    t = t2;
-    k0 = k2;
-  }
-
-  // ---- write back
-  if (W.slot >= 0) {
-    sc_t* P = (sc_t*)part + (long long)W.slot * (TM * TN);
+      if (t2 < W.tend) load(t2, k2);
+      compute(sA, sB);
+      if (!kScaleA && last) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+          for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          P[(wm + a * 16 + acc_row<MODE>(lg, v)) * TN + wn + b * 16 + lr] = acc[a][b][v];
-    return;
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm + a * 16 + acc_row<MODE>(lg, v);
-        const int col = n0 + wn + b * 16 + lr;
-        if (row < J.m && col < J.n) {
-          const long long o = (long long)row * J.ldc + col;
-          if (J.accumulate) {
-            if constexpr (DC == DT_F64) ((double*)J.C)[o] += (double)acc[a][b][v];
-            else stv<DC>(J.C, o, ldv<DC>(J.C, o) + (double)acc[a][b][v]);
-          } else {
-            stv<DC>(J.C, o, acc[a][b][v]);
-          }
-        }
+            for (int v = 0; v < 4; ++v) {
+              acc[a][b][v] += alpha * accp[a][b][v];
+              accp[a][b][v] = 0;
+            }
       }
+      buf ^= 1;
+      t = t2;
+      k0 = k2;
+    }
+    write_back();
+  }
 }
+
 
 // Sum of the partial tiles of split items, in slot order, into C.
 template <int MODE, int DC>
@@ -332,6 +522,14 @@ __global__ __launch_bounds__(256) void reduce_kernel(const RawJob* __restrict__ 
     } else {
       stv<DC>(J.C, o, s);
     }
+  }
+}
+
+template <int DD>
+__global__ void pack_kernel(void* dst, const double* __restrict__ src, const int* __restrict__ idx, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int j = idx[i];
+    stv<DD>(dst, i, j >= 0 ? src[j] : 0.0);
   }
 }
 
@@ -574,21 +772,39 @@ struct Prepared {
   WorkItem* d_items = nullptr;
   RedItem* d_reds = nullptr;
   long long nitems = 0, nreds = 0, nslots = 0;
-  int mode = DT_F64, da = DT_F64, db = DT_F64, dc = DT_F64;
+  int mode = DT_F64, da = DT_F64, db = DT_F64, dc = DT_F64, kt = 16;
 };
 
 using KernelFn = void (*)(const RawJob*, const RawTerm*, const WorkItem*, void*);
 using ReduceFn = void (*)(const RawJob*, const RedItem*, const void*);
 
-KernelFn pick(int mode, int da, int db, int dc) {
-#define K_(M, A, B, C) \
-  if (mode == M && da == A && db == B && dc == C) return gemm_kernel<M, A, B, C>;
-  K_(DT_F64, DT_F64, DT_F64, DT_F64)
-  K_(DT_F32, DT_F32, DT_F32, DT_F32)
-  K_(DT_BF16, DT_BF16, DT_BF16, DT_BF16)
-  K_(DT_BF16, DT_BF16, DT_BF16, DT_F32)
-#undef K_
+KernelFn pick(int mode, int da, int db, int dc, int kt) {
+  if (da != mode || db != mode) throw std::runtime_error("executor: operands must be stored in the arithmetic type");
+  if (mode == DT_F64 && dc == DT_F64) return gemm_kernel<DT_F64, DT_F64, 16>;
+  if (mode == DT_F32 && dc == DT_F32) return gemm_kernel<DT_F32, DT_F32, 16>;
+  if (mode == DT_BF16 && dc == DT_BF16) return kt == 64 ? gemm_kernel<DT_BF16, DT_BF16, 64> : gemm_kernel<DT_BF16, DT_BF16, 32>;
+  if (mode == DT_BF16 && dc == DT_F32) return kt == 64 ? gemm_kernel<DT_BF16, DT_F32, 64> : gemm_kernel<DT_BF16, DT_F32, 32>;
   throw std::runtime_error("executor: unsupported dtype combination");
+}
+
+// K slab of a BF16 launch: 64 when that pads the products' K by at most 1/8
+// more than slabs of 32 would (long products), else 32 (short products, e.g.
+// the K pieces of stage R).  DMRG_BF16_KT=32|64 overrides.
+int choose_kt_bf16(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms) {
+  if (const char* e = std::getenv("DMRG_BF16_KT")) {
+    const int v = std::atoi(e);
+    if (v == 32 || v == 64) return v;
+  }
+  double p32 = 0.0, p64 = 0.0;
+  for (const RawJob& J : jobs) {
+    const double tiles = (double)((J.m + TM - 1) / TM) * (double)((J.n + TN - 1) / TN);
+    for (int64_t t = J.tbeg; t < J.tend; ++t) {
+      if (terms[t].flags & (TF_IDENT_A | TF_IDENT_B)) continue;
+      p32 += tiles * (double)((terms[t].k + 31) / 32 * 32);
+      p64 += tiles * (double)((terms[t].k + 63) / 64 * 64);
+    }
+  }
+  return (p64 <= 1.125 * p32) ? 64 : 32;
 }
 ReduceFn pick_reduce(int mode, int dc) {
   if (mode == DT_F64 && dc == DT_F64) return reduce_kernel<DT_F64, DT_F64>;
@@ -772,12 +988,14 @@ class HipExec : public Executor {
     P->db = db;
     P->dc = dc;
     P->mode = (da == DT_F64) ? DT_F64 : (da == DT_F32 ? DT_F32 : DT_BF16);
-    pick(P->mode, da, db, dc);  // validate
+    P->kt = P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16;
+    pick(P->mode, da, db, dc, P->kt);  // validate
     if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
     std::vector<WorkItem> items;
     std::vector<RedItem> reds;
-    plan_items(jobs, terms, P->mode == DT_BF16 ? 32 : 16, items, reds, P->nslots);
+    plan_items(jobs, terms, P->kt, items, reds, P->nslots);
     P->nitems = (long long)items.size();
+    if (P->nitems > 0x7fffffffLL) throw std::runtime_error("executor: too many work items in one launch");
     P->nreds = (long long)reds.size();
     if (P->nreds) pick_reduce(P->mode, dc);
     if (P->nitems) {
@@ -806,19 +1024,17 @@ class HipExec : public Executor {
   void run(void* h) override {
     auto* P = (Prepared*)h;
     if (!P->nitems) return;
-    KernelFn k = pick(P->mode, P->da, P->db, P->dc);
+    KernelFn k = pick(P->mode, P->da, P->db, P->dc, P->kt);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing_) {
       HIP_OK(hipEventCreate(&e0));
       HIP_OK(hipEventCreate(&e1));
       HIP_OK(hipEventRecord(e0, stream_));
     }
-    const long long maxg = 0x7fffffffLL;
-    for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
-      const long long nt = std::min(maxg, P->nitems - t0);
-      hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0, part_);
-    }
+    // one work-group per item; the hardware dispatcher balances the load
+    hipLaunchKernelGGL(k, dim3((unsigned)P->nitems), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items, part_);
     HIP_OK(hipGetLastError());
+    const long long maxg = 0x7fffffffLL;
     if (P->nreds) {
       ReduceFn r = pick_reduce(P->mode, P->dc);
       for (long long t0 = 0; t0 < P->nreds; t0 += maxg) {
@@ -873,6 +1089,15 @@ class HipExec : public Executor {
                   t_alloc_.s, t_alloc_.n, t_free_.s, t_free_.n, t_up_.s, t_up_.n, t_down_.s, t_down_.n, t_prep_.s,
                   t_prep_.n, t_sync_.s, t_sync_.n);
     return b;
+  }
+  void pack(void* dst, int dd, const double* src, const int* idx, size_t n) override {
+    if (!n) return;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    if (dd == DT_F64) hipLaunchKernelGGL((pack_kernel<DT_F64>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
+    else if (dd == DT_F32) hipLaunchKernelGGL((pack_kernel<DT_F32>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
+    else if (dd == DT_BF16) hipLaunchKernelGGL((pack_kernel<DT_BF16>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
+    else throw std::runtime_error("executor: unsupported pack dtype");
+    HIP_OK(hipGetLastError());
   }
   void convert(void* dst, int dd, const void* src, int ds, size_t n) override {
     if (!n) return;

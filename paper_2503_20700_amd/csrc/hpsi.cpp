@@ -178,10 +178,11 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
     std::vector<GemmJob> jobs;
     for (const auto& ro : O.rows) {  // output row sub (l', s1') [dir 0]  /  (l, s1) [dir 1]
       GemmJob j;
-      j.C = BufRef{-3, base + (int64_t)ro.r0 * In.ncols};  // -3: X placeholder
+      // X rows have the padded column layout of the input super-block
+      j.C = BufRef{-3, base + (int64_t)ro.r0 * In.pncols};  // -3: X placeholder
       j.m = ro.dl;
-      j.n = In.ncols;
-      j.ldc = In.ncols;
+      j.n = In.pncols;
+      j.ldc = In.pncols;
       j.accumulate = 0;
       j.tbeg = (int64_t)ch.stageL.terms.size();
       const Sector& so_sec = L.bond.secs[ro.il];
@@ -214,13 +215,15 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
         gt.flags = 0;
         if (LF) {
           gt.A = BufRef{LF->buf, (int64_t)t.L.idx * LF->lay->size + LF->lay->blocks[blk].off};
-          gt.lda = sk_.dim;  // stored block is D_bra x D_ket
+          gt.lda = LF->lay->blocks[blk].ld;  // stored block is D_bra x D_ket (padded rows)
           if (dir == 1) gt.flags |= TF_TRANS_A;
         } else {
           gt.flags |= TF_IDENT_A;
         }
-        gt.B = BufRef{-1, In.off + (int64_t)ri.r0 * In.ncols};  // -1: psi_in placeholder
-        gt.ldb = In.ncols;
+        gt.B = BufRef{-6, In.poff + (int64_t)ri.r0 * In.pncols};  // -6: padded psi_in placeholder
+        gt.ldb = In.pncols;
+        // operator blocks, padded psi and X all have 8-element padded rows
+        gt.flags |= TF_PAD_B | (LF ? TF_PAD_A : 0);
         gt.k = ri.dl;
         gt.alpha = w * r1;
         ch.stageL.terms.push_back(gt);
@@ -235,7 +238,7 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
     std::pair<int64_t, bool> res{base, any};
     if (any) {
       for (auto& j : jobs) ch.stageL.jobs.push_back(j);
-      xoff += (int64_t)O.nrows * In.ncols;
+      xoff += (int64_t)O.nrows * In.pncols;
     } else {
       ch.stageL.terms.resize(jobs.empty() ? ch.stageL.terms.size() : jobs.front().tbeg);
     }
@@ -300,13 +303,14 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
                                   fsign(RF ? (std::abs(RF->dn) & 1) : 0, kLocN[ks]);
                 if (wR == 0.0) continue;
                 GemmTerm gt;
-                gt.A = BufRef{-3, xbase + ci.c0};
-                gt.lda = Xin.ncols;
-                gt.flags = 0;
+                gt.A = BufRef{-3, xbase + ci.pc0};
+                gt.lda = Xin.pncols;
+                gt.flags = TF_PAD_A;
                 if (RF) {
                   gt.B = BufRef{RF->buf, (int64_t)t.R.idx * RF->lay->size + RF->lay->blocks[blk].off};
-                  gt.ldb = srk.dim;
+                  gt.ldb = RF->lay->blocks[blk].ld;
                   if (d == 0) gt.flags |= TF_TRANS_B;  // X @ R^T ; transposed term: X @ R
+                  gt.flags |= TF_PAD_B;
                 } else {
                   gt.flags |= TF_IDENT_B;
                 }
@@ -376,14 +380,14 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
             GemmTerm gt;
             if (LF) {
               gt.A = BufRef{LF->buf, (int64_t)t.L.idx * LF->lay->size + LF->lay->blocks[lb].off};
-              gt.lda = sl.dim + 1;
+              gt.lda = LF->lay->blocks[lb].ld + 1;  // diagonal stride
             } else {
               gt.A = BufRef{-4, 0};  // ones
               gt.lda = 1;
             }
             if (RF) {
               gt.B = BufRef{RF->buf, (int64_t)t.R.idx * RF->lay->size + RF->lay->blocks[rb].off};
-              gt.ldb = sr.dim + 1;
+              gt.ldb = RF->lay->blocks[rb].ld + 1;
             } else {
               gt.B = BufRef{-4, 0};
               gt.ldb = 1;

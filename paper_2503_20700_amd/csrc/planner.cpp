@@ -33,8 +33,9 @@ const OpLayout& Block::layout(int k2, int dn) {
       const Sector &sb = bond.secs[br], &sk = bond.secs[kt];
       if (sb.n != sk.n + dn || !tri2(sk.s2, k2, sb.s2)) continue;
       lay->lookup[(size_t)br * lay->nsec + kt] = (int)lay->blocks.size();
-      lay->blocks.push_back(OpBlock{br, kt, lay->size});
-      lay->size += (int64_t)sb.dim * sk.dim;
+      const int ld = pad_up(sk.dim);
+      lay->blocks.push_back(OpBlock{br, kt, lay->size, ld});
+      lay->size += (int64_t)sb.dim * ld;
     }
   const OpLayout& ref = *lay;
   layouts[key] = std::move(lay);
@@ -783,7 +784,7 @@ std::unique_ptr<Block> Context::grow_left(Block& L, const SiteTensor& A, const B
                 if (LF) {
                   blk_idx = LF->lay->find(Ab.s0, Ak.s0);
                   if (blk_idx < 0) continue;
-                  lda = slk.dim;
+                  lda = LF->lay->blocks[blk_idx].ld;
                 } else if (Ab.s0 != Ak.s0) {
                   continue;
                 }
@@ -795,7 +796,7 @@ std::unique_ptr<Block> Context::grow_left(Block& L, const SiteTensor& A, const B
                 if (LF) {
                   blk_idx = LF->lay->find(Ak.s0, Ab.s0);
                   if (blk_idx < 0) continue;
-                  lda = slb.dim;
+                  lda = LF->lay->blocks[blk_idx].ld;
                   flags |= TF_TRANS_A;
                 } else if (Ab.s0 != Ak.s0) {
                   continue;
@@ -841,7 +842,7 @@ std::unique_ptr<Block> Context::grow_left(Block& L, const SiteTensor& A, const B
         j2.C = BufRef{F.buf, (int64_t)T.idx * F.lay->size + ob.off};
         j2.m = sa_b.dim;
         j2.n = da;
-        j2.ldc = da;
+        j2.ldc = ob.ld;
         j2.accumulate = 0;
         j2.tbeg = s2_tbeg;
         j2.tend = (int64_t)s2.terms.size();
@@ -944,7 +945,7 @@ std::unique_ptr<Block> Context::grow_right(Block& R, const SiteTensor& B, const 
                 if (RF) {
                   blk_idx = RF->lay->find(Bb.s1, Bk.s1);
                   if (blk_idx < 0) continue;
-                  lda = srk.dim;
+                  lda = RF->lay->blocks[blk_idx].ld;
                 } else if (Bb.s1 != Bk.s1) {
                   continue;
                 }
@@ -956,7 +957,7 @@ std::unique_ptr<Block> Context::grow_right(Block& R, const SiteTensor& B, const 
                 if (RF) {
                   blk_idx = RF->lay->find(Bk.s1, Bb.s1);
                   if (blk_idx < 0) continue;
-                  lda = srb.dim;
+                  lda = RF->lay->blocks[blk_idx].ld;
                   flags |= TF_TRANS_A;
                 } else if (Bb.s1 != Bk.s1) {
                   continue;
@@ -1000,7 +1001,7 @@ std::unique_ptr<Block> Context::grow_right(Block& R, const SiteTensor& B, const 
         j2.C = BufRef{F.buf, (int64_t)T.idx * F.lay->size + ob.off};
         j2.m = sc_b.dim;
         j2.n = dc;
-        j2.ldc = dc;
+        j2.ldc = ob.ld;
         j2.accumulate = 0;
         j2.tbeg = s2_tbeg;
         j2.tend = (int64_t)s2.terms.size();
@@ -1037,7 +1038,7 @@ void PsiLayout::build(const Bond& lb, const Bond& rb, int n_elec, int two_s) {
   for (auto& [an, as2] : akeys)
     for (auto& [cn, cs2] : ckeys) {
       if (an + cn != n_elec || !tri2(as2, cs2, two_s)) continue;
-      SB sb{an, as2, cn, cs2, 0, 0, 0, {}, {}};
+      SB sb{an, as2, cn, cs2, 0, 0, 0, 0, 0, {}, {}};
       for (size_t il = 0; il < lb.secs.size(); ++il)
         for (int s1 = 0; s1 < 3; ++s1) {
           const Sector& s = lb.secs[il];
@@ -1050,15 +1051,28 @@ void PsiLayout::build(const Bond& lb, const Bond& rb, int n_elec, int two_s) {
         for (size_t ir = 0; ir < rb.secs.size(); ++ir) {
           const Sector& s = rb.secs[ir];
           if (kLocN[s2] + s.n == cn && tri2(kLocS2[s2], s.s2, cs2) && s.dim > 0) {
-            sb.cols.push_back(Col{s2, (int)ir, sb.ncols, s.dim});
+            sb.cols.push_back(Col{s2, (int)ir, sb.ncols, s.dim, sb.pncols});
             sb.ncols += s.dim;
+            sb.pncols += pad_up(s.dim);
           }
         }
       if (sb.nrows == 0 || sb.ncols == 0) continue;
       sb.off = size;
       size += (int64_t)sb.nrows * sb.ncols;
+      sb.poff = psize;
+      psize += (int64_t)sb.nrows * sb.pncols;
       sbs.push_back(sb);
     }
+}
+
+std::vector<int> PsiLayout::pack_map() const {
+  std::vector<int> m((size_t)psize, -1);
+  for (const SB& sb : sbs)
+    for (int r = 0; r < sb.nrows; ++r)
+      for (const Col& c : sb.cols)
+        for (int q = 0; q < c.dr; ++q)
+          m[(size_t)(sb.poff + (int64_t)r * sb.pncols + c.pc0 + q)] = (int)(sb.off + (int64_t)r * sb.ncols + c.c0 + q);
+  return m;
 }
 
 }  // namespace dmrg

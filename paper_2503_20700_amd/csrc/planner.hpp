@@ -42,9 +42,16 @@ struct Bond {
   int find(int n, int s2) const;
 };
 
+// Operator blocks are stored row-major with the row stride padded to a
+// multiple of 8 elements and 8-element aligned offsets, so that every row of
+// every block starts on a 16-byte boundary in all precisions (vector loads in
+// the H*psi kernels).  Padding elements are never read as data.
+constexpr int kPad = 8;
+inline int pad_up(int d) { return (d + kPad - 1) / kPad * kPad; }
 struct OpBlock {
   int bra = 0, ket = 0;
   int64_t off = 0;
+  int ld = 0;  // row stride (>= ket dimension)
 };
 
 struct OpLayout {
@@ -159,21 +166,27 @@ struct SiteTensor {
 };
 
 // Two-site wavefunction layout (super-blocks, see the ABI header).
+// psi in the caller's layout (dense super-blocks) and, for the contraction
+// kernels, a padded copy in which every column sub-block starts on a multiple
+// of 8 elements (pc0), rows have stride pncols (a multiple of 8) and
+// super-blocks start at 8-aligned offsets poff; padding holds zeros.
 struct PsiLayout {
   struct Row {
     int il, s1, r0, dl;
   };
   struct Col {
-    int s2, ir, c0, dr;
+    int s2, ir, c0, dr, pc0;
   };
   struct SB {
-    int an, as2, cn, cs2, nrows, ncols;
-    int64_t off;
+    int an, as2, cn, cs2, nrows, ncols, pncols;
+    int64_t off, poff;
     std::vector<Row> rows;
     std::vector<Col> cols;
   };
   std::vector<SB> sbs;
-  int64_t size = 0;
+  int64_t size = 0, psize = 0;
+  // padded index -> caller index (-1 for padding)
+  std::vector<int> pack_map() const;
   void build(const Bond& lb, const Bond& rb, int n_elec, int two_s);
 };
 

@@ -11,15 +11,17 @@
 // Record the thread-local error message returned by dmrg_last_error().
 int dmrg_fail(int code, const std::string& msg);
 
-// psi_in, psi_out, X, ones, diag placeholders used by the H*psi task lists
-enum { PH_IN = 1, PH_OUT = 2, PH_X = 3, PH_ONES = 4, PH_DIAG = 5 };
+// psi_in, psi_out, X, ones, diag and padded-psi_in placeholders used by the
+// H*psi task lists
+enum { PH_IN = 1, PH_OUT = 2, PH_X = 3, PH_ONES = 4, PH_DIAG = 5, PH_INP = 6 };
 
 struct dmrg_ctx {
   dmrg_opts opts{};
   std::unique_ptr<dmrg::Executor> ex;
   std::unique_ptr<dmrg::Context> C;
   std::unique_ptr<dmrg::HpsiPlan> plan;
-  int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1;
+  int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1, b_inp = -1;
+  void* d_pidx = nullptr;  // padded psi index -> caller index (int32, -1 = padding)
   struct Prepared {
     std::vector<void*> L, R;
     bool ready = false;
@@ -56,7 +58,9 @@ struct dmrg_ctx {
       work_bufs.clear();
       work_n = 0;
       work_mmax = 0;
-      for (int b : {b_in, b_out, b_x, b_ones, b_diag}) C->free_buf(b);
+      for (int b : {b_in, b_out, b_x, b_ones, b_diag, b_inp}) C->free_buf(b);
+      if (d_pidx) ex->release(d_pidx);
+      d_pidx = nullptr;
       if (C->Lblk) {
         for (auto& t : C->Lblk->tmp) C->free_buf(t.buf);
         C->Lblk->tmp.clear();
@@ -66,7 +70,7 @@ struct dmrg_ctx {
         C->Rblk->tmp.clear();
       }
     }
-    b_in = b_out = b_x = b_ones = b_diag = -1;
+    b_in = b_out = b_x = b_ones = b_diag = b_inp = -1;
     plan.reset();
   }
 
@@ -76,6 +80,7 @@ struct dmrg_ctx {
     C->ph[PH_X] = b_x;
     C->ph[PH_ONES] = b_ones;
     C->ph[PH_DIAG] = b_diag;
+    C->ph[PH_INP] = b_inp;
   }
 
   void ensure_plan() {
@@ -86,6 +91,12 @@ struct dmrg_ctx {
     b_out = C->new_buf(std::max<int64_t>(n, 1));
     b_x = C->new_buf(std::max<int64_t>(plan->xmax, 1));
     b_diag = C->new_buf(std::max<int64_t>(n, 1));
+    b_inp = C->new_buf(std::max<int64_t>(plan->lay.psize, 1));
+    {
+      const std::vector<int> m = plan->lay.pack_map();
+      d_pidx = ex->alloc(std::max<size_t>(m.size(), 1) * sizeof(int));
+      if (!m.empty()) ex->upload(d_pidx, m.data(), m.size() * sizeof(int));
+    }
     int maxd = 1;
     for (auto& bd : C->bonds)
       for (auto& s : bd.secs) maxd = std::max(maxd, s.dim);
@@ -111,6 +122,7 @@ struct dmrg_ctx {
           if (t.buf >= 0) C->ensure_dtype(t.buf, od);
       }
       C->alloc_dtype(b_in, od);
+      C->alloc_dtype(b_inp, od);
       C->alloc_dtype(b_x, xd);
       C->alloc_dtype(b_out, outd);
     }
@@ -131,7 +143,7 @@ struct dmrg_ctx {
     prepare(prec);
     const int64_t n = plan->lay.size;
     const int od = op_dt(prec), outd = out_dt(prec);
-    if (od != dmrg::DT_F64) ex->convert(C->ptr(b_in, od), od, C->ptr(b_in), dmrg::DT_F64, (size_t)n);
+    ex->pack(C->ptr(b_inp, od), od, (const double*)C->ptr(b_in), (const int*)d_pidx, (size_t)plan->lay.psize);
     ex->zero(C->ptr(b_out, outd), (size_t)n * dmrg::dtype_size(outd));
     Prepared& P = prep[prec];
     for (size_t i = 0; i < P.L.size(); ++i) {

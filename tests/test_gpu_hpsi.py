@@ -69,8 +69,11 @@ def test_heff_diag_matches_oracle_dense():
     assert np.abs(diag - np.diag(hd)).max() < 1e-10 * np.abs(np.diag(hd)).max()
 
 
-@pytest.mark.parametrize("prec,bound", [(1, 2.0 ** -24 * 64), (2, 2.0 ** -8 * 8)])
-def test_hpsi_low_precision_error_bound(prec, bound):
+@pytest.mark.parametrize("prec,bound,kt", [(1, 2.0 ** -24 * 64, ""), (2, 2.0 ** -8 * 8, "32"),
+                                           (2, 2.0 ** -8 * 8, "64"), (2, 2.0 ** -8 * 8, "")])
+def test_hpsi_low_precision_error_bound(prec, bound, kt, monkeypatch):
+    if kt:
+        monkeypatch.setenv("DMRG_BF16_KT", kt)  # else chosen per launch
     case = (10, 10, 0, 40, 4, 6)
     h, g, mps, psi, lay, dm = _setup(*case)
     y64, _ = dm.hpsi(psi, 0)

@@ -35,9 +35,10 @@ def test_gemm_identity_operands(m, n):
     assert np.abs(got - 0.5 * a).max() < 1e-14
 
 
-@pytest.mark.parametrize("prec,eps", [(1, 2.0 ** -24), (2, 2.0 ** -8)])
+@pytest.mark.parametrize("prec,eps,kt", [(1, 2.0 ** -24, "32"), (2, 2.0 ** -8, "32"), (2, 2.0 ** -8, "64")])
 @pytest.mark.parametrize("m,n,k", [(65, 63, 17), (130, 70, 300)])
-def test_gemm_low_precision(prec, eps, m, n, k):
+def test_gemm_low_precision(prec, eps, kt, m, n, k, monkeypatch):
+    monkeypatch.setenv("DMRG_BF16_KT", kt)
     from paper_2503_20700_amd.binding import gemm_selftest
     rng = np.random.default_rng(5)
     a = rng.normal(size=(m, k))
@@ -47,3 +48,29 @@ def test_gemm_low_precision(prec, eps, m, n, k):
     # |error| <= ~2 eps * sum_k |a||b| (operand rounding) + k * 2^-24 * ... (fp32 accumulation)
     bound = (2 * eps + k * 2.0 ** -24) * (np.abs(a) @ np.abs(b))
     assert np.all(np.abs(got - ref) <= 4 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("prec,kt", [(0, "32"), (1, "32"), (2, "32"), (2, "64")])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (64, 64, 32), (65, 63, 17), (130, 70, 33), (7, 200, 129), (200, 9, 5)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_padded_vector_path(prec, kt, m, n, k, ta, tb, monkeypatch):
+    # Rows padded to a multiple of 8 with NaN padding: the 16-byte vector
+    # loads must mask everything past the logical extent (a leaked NaN fails).
+    # BF16 runs with K slabs of 32 and of 64.
+    monkeypatch.setenv("DMRG_BF16_KT", kt)
+    from paper_2503_20700_amd.binding import gemm_selftest
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    a = rng.normal(size=(m, k))
+    b = rng.normal(size=(k, n))
+    c0 = rng.normal(size=(m, n))
+    for pa, pb in [(True, True), (True, False), (False, True)]:
+        got = gemm_selftest(a.T.copy() if ta else a, b.T.copy() if tb else b, C=c0, trans_a=bool(ta),
+                            trans_b=bool(tb), alpha=0.75, beta=1.0, prec=prec, pad_a=pa, pad_b=pb)
+        ref = c0 + 0.75 * (a @ b)
+        assert np.all(np.isfinite(got))
+        if prec == 0:
+            assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+        else:
+            eps = 2.0 ** -24 if prec == 1 else 2.0 ** -8
+            bound = (2 * eps + k * 2.0 ** -24) * 0.75 * (np.abs(a) @ np.abs(b)) + 2.0 ** -24 * np.abs(ref)
+            assert np.all(np.abs(got - ref) <= 4 * bound + 1e-30)
