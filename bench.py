@@ -115,6 +115,10 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true", help="skip the converged mixed-vs-FP64 case")
     ap.add_argument("--dav-lo", type=int, default=8, help="BF16 Davidson iterations in the DMRG step")
     ap.add_argument("--dav-hi", type=int, default=3, help="FP64 refinement iterations in the DMRG step")
+    ap.add_argument("--x-budget", type=int, default=0, metavar="ELEMS",
+                    help="cap on the X intermediates of one H*psi chunk (elements; 0: library default)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1", file=sys.stderr)
@@ -125,13 +129,22 @@ def main():
     from synth.mps import random_mps, random_psi
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 17  # float64 elements in MIB MiB
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
+        del src, dst
     w = workload(args.config)
     t0 = time.perf_counter()
     mps = random_mps(w["n"], w["N"], w["two_s"], w["D"], k=w["k"], seed=w["seed"])
     psi, lay = random_psi(mps, seed=w["seed"] + 1)
     log(f"{w['name']}: MPS drawn in {time.perf_counter() - t0:.1f}s, psi has {psi.size} coefficients")
     dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=BF16, davidson_max_iter=args.dav_lo,
-              davidson_refine_iter=args.dav_hi)
+              davidson_refine_iter=args.dav_hi, work_budget_elems=args.x_budget)
     bs, cnt = mps.bond_table()
     t0 = time.perf_counter()
     dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())

@@ -21,6 +21,8 @@
 #include <unordered_map>
 #include <cstdio>
 #include <type_traits>
+#include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <stdexcept>
@@ -502,6 +504,227 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
 }
 
 
+// BF16 kernel for launches whose dense products all have padded, 16-byte
+// aligned operands (the two stages of H*psi).  Same work items, tiles and
+// MFMA layout as gemm_kernel, with a lean K loop:
+//   * each thread keeps a pointer cursor per operand for the product being
+//     loaded, set once per product and advanced by one slab per step;
+//   * every thread owns one 16-byte vector of each slab (rows along the
+//     operand's contiguous dimension), with LDS offsets fixed per thread;
+//   * product weights use a scaled frame: the accumulator holds the partial
+//     sum divided by the weight of the product being multiplied, rescaled by
+//     w_prev / w_next (FP32) when a new product starts and by the last weight
+//     before write-back, so no second accumulator is needed.
+template <int DC>
+__global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict__ jobs,
+                                                        const RawTerm* __restrict__ terms,
+                                                        const WorkItem* __restrict__ items, void* __restrict__ part) {
+  constexpr int KT = 32, LS = KT + 8;  // LDS row stride in bf16 elements (80 bytes)
+  __shared__ __attribute__((aligned(16))) u16 sm[2][2][TM * LS];
+  const int tid = threadIdx.x;
+  const WorkItem W = items[blockIdx.x];
+  const RawJob J = jobs[W.job];
+  const int m0 = W.ti * TM, n0 = W.tj * TN;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  // identity products, in the unscaled frame
+  for (int t = W.tbeg; t < W.tend; ++t) {
+    const int fl = terms[t].flags;
+    if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+    const RawTerm T = terms[t];
+    const bool ia = fl & TF_IDENT_A;
+    const u16* P = (const u16*)(ia ? T.B : T.A);
+    const long long ld = ia ? T.ldb : T.lda;
+    const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = m0 + wm + a * 16 + 4 * lg + v;
+          const int col = n0 + wn + b * 16 + lr;
+          if (row < J.m && col < J.n)
+            acc[a][b][v] += (float)T.alpha * bf2f(P[tr ? (long long)col * ld + row : (long long)row * ld + col]);
+        }
+  }
+  // thread roles: "K" = 64 rows x 4 vectors along k; "MN" = 32 k-rows x 8 vectors along m (n)
+  const int rK = tid >> 2, kvK = (tid & 3) * 8;
+  const int kMN = tid >> 3, vMN = (tid & 7) * 8;
+  const int offK = rK * LS + kvK;
+  const int offMN = vMN * LS + kMN;
+
+  // load cursor (product whose slabs are being loaded)
+  const u16* pa = nullptr;
+  const u16* pb = nullptr;
+  long long stepA = 0, stepB = 0;
+  bool aK = true, bK = true, okA = false, okB = false;
+  int nvA = 8, nvB = 8;
+  auto begin = [&](const RawTerm& T) {
+    aK = !(T.flags & TF_TRANS_A);  // A stored m x k (k contiguous)
+    bK = (T.flags & TF_TRANS_B);   // B stored n x k (k contiguous)
+    const u16* A = (const u16*)T.A;
+    const u16* B = (const u16*)T.B;
+    if (aK) {
+      okA = m0 + rK < J.m;
+      pa = A + (long long)(m0 + rK) * T.lda + kvK;
+      stepA = KT;
+    } else {
+      nvA = min(max(J.m - (m0 + vMN), 0), 8);
+      pa = A + (long long)kMN * T.lda + m0 + vMN;
+      stepA = (long long)KT * T.lda;
+    }
+    if (bK) {
+      okB = n0 + rK < J.n;
+      pb = B + (long long)(n0 + rK) * T.ldb + kvK;
+      stepB = KT;
+    } else {
+      nvB = min(max(J.n - (n0 + vMN), 0), 8);
+      pb = B + (long long)kMN * T.ldb + n0 + vMN;
+      stepB = (long long)KT * T.ldb;
+    }
+  };
+  uint4 ra, rb;
+  const uint4 z4 = make_uint4(0, 0, 0, 0);
+  auto load = [&](int K, int k0) {
+    if (aK) {
+      const int nv = K - (k0 + kvK);
+      ra = (okA && nv > 0) ? *(const uint4*)pa : z4;
+      if (nv < 8) ra = keep_first<2>(ra, nv);
+    } else {
+      ra = (k0 + kMN < K && nvA > 0) ? *(const uint4*)pa : z4;
+      if (nvA < 8) ra = keep_first<2>(ra, nvA);
+    }
+    if (bK) {
+      const int nv = K - (k0 + kvK);
+      rb = (okB && nv > 0) ? *(const uint4*)pb : z4;
+      if (nv < 8) rb = keep_first<2>(rb, nv);
+    } else {
+      rb = (k0 + kMN < K && nvB > 0) ? *(const uint4*)pb : z4;
+      if (nvB < 8) rb = keep_first<2>(rb, nvB);
+    }
+    pa += stepA;
+    pb += stepB;
+  };
+  bool sK_A = true, sK_B = true;  // layout of the registers being stored
+  auto store = [&](u16* sA, u16* sB) {
+    if (sK_A) {
+      *(uint4*)(sA + offK) = ra;
+    } else {
+      const unsigned w[4] = {ra.x, ra.y, ra.z, ra.w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sA[offMN + q * LS] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+    }
+    if (sK_B) {
+      *(uint4*)(sB + offK) = rb;
+    } else {
+      const unsigned w[4] = {rb.x, rb.y, rb.z, rb.w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sB[offMN + q * LS] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+    }
+  };
+  const int rdA0 = (wm + lr) * LS + 8 * lg, rdA1 = rdA0 + 16 * LS;
+  const int rdB0 = (wn + lr) * LS + 8 * lg, rdB1 = rdB0 + 16 * LS;
+
+  auto next_dense = [&](int t) {
+    while (t < W.tend && (terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) ++t;
+    return t;
+  };
+  int t = next_dense(W.tbeg), k0 = 0;
+  int Kc = 0;
+  float alpha = 1.f, scale = 1.f;  // weight of product t; current frame of acc
+  if (t < W.tend) {
+    const RawTerm T = terms[t];
+    Kc = T.k;
+    alpha = (float)T.alpha;
+    begin(T);
+    load(Kc, 0);
+    sK_A = aK;
+    sK_B = bK;
+  }
+  int buf = 0;
+  while (t < W.tend) {
+    u16* sA = sm[buf][0];
+    u16* sB = sm[buf][1];
+    store(sA, sB);
+    __syncthreads();
+    // next slab: same product, or the first slab of the next dense product
+    int t2 = t, k2 = k0 + KT, K2 = Kc;
+    float alpha2 = alpha;
+    if (k2 >= Kc) {
+      t2 = next_dense(t + 1);
+      k2 = 0;
+      if (t2 < W.tend) {
+        const RawTerm T = terms[t2];
+        K2 = T.k;
+        alpha2 = (float)T.alpha;
+        begin(T);
+      }
+    }
+    if (t2 < W.tend) load(K2, k2);
+    if (k0 == 0 && alpha != scale) {
+      // product t starts: move the accumulator into its frame
+      const float r = scale / alpha;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] *= r;
+      scale = alpha;
+    }
+    bf8 av0 = *(const bf8*)(sA + rdA0), av1 = *(const bf8*)(sA + rdA1);
+    bf8 bv0 = *(const bf8*)(sB + rdB0), bv1 = *(const bf8*)(sB + rdB1);
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bv0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bv1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, bv0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, bv1, acc[1][1], 0, 0, 0);
+    sK_A = aK;
+    sK_B = bK;
+    buf ^= 1;
+    t = t2;
+    k0 = k2;
+    Kc = K2;
+    alpha = alpha2;
+  }
+  if (scale != 1.f) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] *= scale;
+  }
+  // write back (C, or the item's partial slot)
+  if (W.slot >= 0) {
+    float* P = (float*)part + (long long)W.slot * (TM * TN);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[(wm + a * 16 + 4 * lg + v) * TN + wn + b * 16 + lr] = acc[a][b][v];
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + a * 16 + 4 * lg + v;
+        const int col = n0 + wn + b * 16 + lr;
+        if (row < J.m && col < J.n) {
+          const long long o = (long long)row * J.ldc + col;
+          if (J.accumulate) stv<DC>(J.C, o, ldv<DC>(J.C, o) + (double)acc[a][b][v]);
+          else stv<DC>(J.C, o, acc[a][b][v]);
+        }
+      }
+}
+
 // Sum of the partial tiles of split items, in slot order, into C.
 template <int MODE, int DC>
 __global__ __launch_bounds__(256) void reduce_kernel(const RawJob* __restrict__ jobs, const RedItem* __restrict__ items,
@@ -773,6 +996,7 @@ struct Prepared {
   RedItem* d_reds = nullptr;
   long long nitems = 0, nreds = 0, nslots = 0;
   int mode = DT_F64, da = DT_F64, db = DT_F64, dc = DT_F64, kt = 16;
+  bool padded = false;  // BF16 launch served by gemm_bf16_padded
 };
 
 using KernelFn = void (*)(const RawJob*, const RawTerm*, const WorkItem*, void*);
@@ -988,7 +1212,21 @@ class HipExec : public Executor {
     P->db = db;
     P->dc = dc;
     P->mode = (da == DT_F64) ? DT_F64 : (da == DT_F32 ? DT_F32 : DT_BF16);
-    P->kt = P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16;
+    if (P->mode == DT_BF16 && (dc == DT_BF16 || dc == DT_F32)) {
+      bool ok = true;
+      for (const RawTerm& T : terms) {
+        if (T.flags & (TF_IDENT_A | TF_IDENT_B)) continue;
+        // the scaled-frame accumulation needs weights whose ratios stay in FP32 range
+        const double aw = std::fabs(T.alpha);
+        if (!(T.flags & TF_PAD_A) || !(T.flags & TF_PAD_B) || ((uintptr_t)T.A & 15) || ((uintptr_t)T.B & 15) ||
+            (T.lda & 7) || (T.ldb & 7) || !(aw >= 1e-12 && aw <= 1e12)) {
+          ok = false;
+          break;
+        }
+      }
+      P->padded = ok && !std::getenv("DMRG_NO_PADDED_KERNEL");
+    }
+    P->kt = P->padded ? 32 : (P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16);
     pick(P->mode, da, db, dc, P->kt);  // validate
     if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
     std::vector<WorkItem> items;
@@ -1024,7 +1262,8 @@ class HipExec : public Executor {
   void run(void* h) override {
     auto* P = (Prepared*)h;
     if (!P->nitems) return;
-    KernelFn k = pick(P->mode, P->da, P->db, P->dc, P->kt);
+    KernelFn k = P->padded ? (P->dc == DT_BF16 ? gemm_bf16_padded<DT_BF16> : gemm_bf16_padded<DT_F32>)
+                           : pick(P->mode, P->da, P->db, P->dc, P->kt);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing_) {
       HIP_OK(hipEventCreate(&e0));

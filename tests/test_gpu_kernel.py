@@ -74,3 +74,17 @@ def test_gemm_padded_vector_path(prec, kt, m, n, k, ta, tb, monkeypatch):
             eps = 2.0 ** -24 if prec == 1 else 2.0 ** -8
             bound = (2 * eps + k * 2.0 ** -24) * 0.75 * (np.abs(a) @ np.abs(b)) + 2.0 ** -24 * np.abs(ref)
             assert np.all(np.abs(got - ref) <= 4 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("m,n,k", [(65, 63, 17), (130, 70, 300), (7, 200, 129)])
+def test_gemm_bf16_lean_and_generic_kernels_agree(m, n, k, monkeypatch):
+    # Fully padded BF16 operands run on the lean kernel; with it switched off
+    # the generic kernel computes the same product (both accumulate in FP32).
+    from paper_2503_20700_amd.binding import gemm_selftest
+    rng = np.random.default_rng(11)
+    a = rng.normal(size=(m, k))
+    b = rng.normal(size=(k, n))
+    lean = gemm_selftest(a, b, alpha=-1.25, prec=2, pad_a=True, pad_b=True)
+    monkeypatch.setenv("DMRG_NO_PADDED_KERNEL", "1")
+    generic = gemm_selftest(a, b, alpha=-1.25, prec=2, pad_a=True, pad_b=True)
+    assert np.abs(lean - generic).max() <= 1e-5 * np.abs(generic).max()
