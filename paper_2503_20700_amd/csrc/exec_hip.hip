@@ -47,12 +47,8 @@ typedef unsigned short u16;
 
 constexpr int TM = 64, TN = 64;
 
-__device__ __forceinline__ u16 f2bf(float f) {
-  unsigned int b = __float_as_uint(f);
-  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (u16)((b >> 16) | 0x40);  // quiet NaN
-  b += 0x7fffu + ((b >> 16) & 1u);
-  return (u16)(b >> 16);
-}
+// FP32 -> BF16, round to nearest even (hardware conversion on gfx950).
+__device__ __forceinline__ u16 f2bf(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
 __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float(((unsigned int)h) << 16); }
 
 template <int DT>
@@ -100,6 +96,8 @@ __device__ __forceinline__ S raw_to(typename raw_of<DT>::T r) {
 // reduction launch adds the job's slots in order (deterministic split-K).
 struct WorkItem {
   int job, ti, tj, tbeg, tend, slot;
+  int dense0;     // first product in [tbeg, tend) that is not an identity (tend if none)
+  int has_ident;  // the range holds identity products
 };
 struct RedItem {
   int job, ti, tj, slot0, nslot, pad;
@@ -535,6 +533,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
   // identity products, in the unscaled frame
+  if (W.has_ident)
   for (int t = W.tbeg; t < W.tend; ++t) {
     const int fl = terms[t].flags;
     if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
@@ -555,11 +554,16 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
             acc[a][b][v] += (float)T.alpha * bf2f(P[tr ? (long long)col * ld + row : (long long)row * ld + col]);
         }
   }
-  // thread roles: "K" = 64 rows x 4 vectors along k; "MN" = 32 k-rows x 8 vectors along m (n)
+  // thread roles: "K" = 64 rows x 4 vectors along k; "MN" = 32 k-rows x 8 vectors along m (n).
+  // LDS row j holds its four 8-element k groups in the order g ^ ((j >> 4) & 3):
+  // rows 16 apart (same banks at the 80-byte stride) get different groups.
+  auto lds_at = [](int j, int k) { return j * LS + 8 * ((k >> 3) ^ ((j >> 4) & 3)) + (k & 7); };
   const int rK = tid >> 2, kvK = (tid & 3) * 8;
   const int kMN = tid >> 3, vMN = (tid & 7) * 8;
-  const int offK = rK * LS + kvK;
-  const int offMN = vMN * LS + kMN;
+  const int offK = lds_at(rK, kvK);
+  int offMN[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) offMN[q] = lds_at(vMN + q, kMN);
 
   // load cursor (product whose slabs are being loaded)
   const u16* pa = nullptr;
@@ -620,24 +624,24 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
     } else {
       const unsigned w[4] = {ra.x, ra.y, ra.z, ra.w};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sA[offMN + q * LS] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+      for (int q = 0; q < 8; ++q) sA[offMN[q]] = (u16)(w[q >> 1] >> (16 * (q & 1)));
     }
     if (sK_B) {
       *(uint4*)(sB + offK) = rb;
     } else {
       const unsigned w[4] = {rb.x, rb.y, rb.z, rb.w};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sB[offMN + q * LS] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+      for (int q = 0; q < 8; ++q) sB[offMN[q]] = (u16)(w[q >> 1] >> (16 * (q & 1)));
     }
   };
-  const int rdA0 = (wm + lr) * LS + 8 * lg, rdA1 = rdA0 + 16 * LS;
-  const int rdB0 = (wn + lr) * LS + 8 * lg, rdB1 = rdB0 + 16 * LS;
+  const int rdA0 = lds_at(wm + lr, 8 * lg), rdA1 = lds_at(wm + 16 + lr, 8 * lg);
+  const int rdB0 = lds_at(wn + lr, 8 * lg), rdB1 = lds_at(wn + 16 + lr, 8 * lg);
 
   auto next_dense = [&](int t) {
     while (t < W.tend && (terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) ++t;
     return t;
   };
-  int t = next_dense(W.tbeg), k0 = 0;
+  int t = W.dense0, k0 = 0;
   int Kc = 0;
   float alpha = 1.f, scale = 1.f;  // weight of product t; current frame of acc
   if (t < W.tend) {
@@ -1084,15 +1088,26 @@ void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& ter
     segs.push_back({(int)s0, (int)J.tend});
     scost.push_back(c);
     const int tm = (J.m + TM - 1) / TM, tn = (J.n + TN - 1) / TN;
+    // per segment: first dense product and whether identities occur
+    std::vector<int> d0(segs.size()), hid(segs.size());
+    for (size_t q = 0; q < segs.size(); ++q) {
+      d0[q] = segs[q].second;
+      hid[q] = 0;
+      for (int t = segs[q].first; t < segs[q].second; ++t) {
+        if (terms[t].flags & (TF_IDENT_A | TF_IDENT_B)) hid[q] = 1;
+        else if (d0[q] == segs[q].second) d0[q] = t;
+      }
+    }
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
         if (segs.size() == 1) {
-          work.push_back({scost[0], WorkItem{(int)j, a, b, segs[0].first, segs[0].second, -1}});
+          work.push_back({scost[0], WorkItem{(int)j, a, b, segs[0].first, segs[0].second, -1, d0[0], hid[0]}});
           continue;
         }
         reds.push_back(RedItem{(int)j, a, b, (int)nslots, (int)segs.size(), 0});
         for (size_t q = 0; q < segs.size(); ++q)
-          work.push_back({scost[q], WorkItem{(int)j, a, b, segs[q].first, segs[q].second, (int)(nslots + q)}});
+          work.push_back({scost[q], WorkItem{(int)j, a, b, segs[q].first, segs[q].second, (int)(nslots + q), d0[q],
+                                             hid[q]}});
         nslots += (long long)segs.size();
       }
   }
