@@ -503,139 +503,182 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
 
 
 // BF16 kernel for launches whose dense products all have padded, 16-byte
-// aligned operands (the two stages of H*psi).  Same work items, tiles and
-// MFMA layout as gemm_kernel, with a lean K loop:
-//   * each thread keeps a pointer cursor per operand for the product being
-//     loaded, set once per product and advanced by one slab per step;
-//   * every thread owns one 16-byte vector of each slab (rows along the
+// aligned operands (the two stages of H*psi).  Same work items and MFMA
+// layout as gemm_kernel, with output tiles of BM x BN (64 or 128 each; four
+// waves in a 2 x 2 grid, each owning a (BM/2) x (BN/2) quadrant) and a lean
+// K loop:
+//   * each thread keeps a pointer cursor per operand vector for the product
+//     being loaded, set once per product and advanced by one slab per step;
+//   * every thread owns fixed 16-byte vectors of each slab (rows along the
 //     operand's contiguous dimension), with LDS offsets fixed per thread;
+//   * LDS rows hold their four 8-element k groups in the order
+//     g ^ ((row >> 4) & 3), so rows 16 apart (same banks at the 80-byte row
+//     stride) use different banks for transposed stores;
 //   * product weights use a scaled frame: the accumulator holds the partial
 //     sum divided by the weight of the product being multiplied, rescaled by
 //     w_prev / w_next (FP32) when a new product starts and by the last weight
 //     before write-back, so no second accumulator is needed.
-template <int DC>
+template <int DC, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict__ jobs,
                                                         const RawTerm* __restrict__ terms,
                                                         const WorkItem* __restrict__ items, void* __restrict__ part) {
-  constexpr int KT = 32, LS = KT + 8;  // LDS row stride in bf16 elements (80 bytes)
-  __shared__ __attribute__((aligned(16))) u16 sm[2][2][TM * LS];
+  constexpr int KT = 32, LS = KT + 8;     // LDS row stride in bf16 elements (80 bytes)
+  constexpr int NA = BM / 64, NB = BN / 64;  // 16-byte vectors per thread per slab
+  constexpr int FA = BM / 32, FB = BN / 32;  // 16x16 MFMA blocks per wave along m / n
+  __shared__ __attribute__((aligned(16))) u16 sA_[2][BM * LS];
+  __shared__ __attribute__((aligned(16))) u16 sB_[2][BN * LS];
   const int tid = threadIdx.x;
   const WorkItem W = items[blockIdx.x];
   const RawJob J = jobs[W.job];
-  const int m0 = W.ti * TM, n0 = W.tj * TN;
+  const int m0 = W.ti * BM, n0 = W.tj * BN;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
   const int lr = lane & 15, lg = lane >> 4;
 
-  f4 acc[2][2];
+  f4 acc[FA][FB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < FB; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
   // identity products, in the unscaled frame
   if (W.has_ident)
-  for (int t = W.tbeg; t < W.tend; ++t) {
-    const int fl = terms[t].flags;
-    if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
-    const RawTerm T = terms[t];
-    const bool ia = fl & TF_IDENT_A;
-    const u16* P = (const u16*)(ia ? T.B : T.A);
-    const long long ld = ia ? T.ldb : T.lda;
-    const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+    for (int t = W.tbeg; t < W.tend; ++t) {
+      const int fl = terms[t].flags;
+      if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+      const RawTerm T = terms[t];
+      const bool ia = fl & TF_IDENT_A;
+      const u16* P = (const u16*)(ia ? T.B : T.A);
+      const long long ld = ia ? T.ldb : T.lda;
+      const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < FA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FB; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = m0 + wm + a * 16 + 4 * lg + v;
-          const int col = n0 + wn + b * 16 + lr;
-          if (row < J.m && col < J.n)
-            acc[a][b][v] += (float)T.alpha * bf2f(P[tr ? (long long)col * ld + row : (long long)row * ld + col]);
-        }
-  }
-  // thread roles: "K" = 64 rows x 4 vectors along k; "MN" = 32 k-rows x 8 vectors along m (n).
-  // LDS row j holds its four 8-element k groups in the order g ^ ((j >> 4) & 3):
-  // rows 16 apart (same banks at the 80-byte stride) get different groups.
+          for (int v = 0; v < 4; ++v) {
+            const int row = m0 + wm + a * 16 + 4 * lg + v;
+            const int col = n0 + wn + b * 16 + lr;
+            if (row < J.m && col < J.n)
+              acc[a][b][v] += (float)T.alpha * bf2f(P[tr ? (long long)col * ld + row : (long long)row * ld + col]);
+          }
+    }
   auto lds_at = [](int j, int k) { return j * LS + 8 * ((k >> 3) ^ ((j >> 4) & 3)) + (k & 7); };
-  const int rK = tid >> 2, kvK = (tid & 3) * 8;
-  const int kMN = tid >> 3, vMN = (tid & 7) * 8;
-  const int offK = lds_at(rK, kvK);
-  int offMN[8];
+  // thread roles for vector v of an operand with R rows (R = BM or BN):
+  //   "K":  row (tid + 256 v) >> 2, k offset ((tid + 256 v) & 3) * 8
+  //   "MN": k row (tid + 256 v) / (R / 8), offset ((tid + 256 v) % (R / 8)) * 8 along m (n)
+  const int kvK = (tid & 3) * 8;
+  int offAK[NA], offBK[NB], offAM[NA][8], offBM[NB][8], kAM[NA], vAM[NA], kBM[NB], vBM[NB];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) offMN[q] = lds_at(vMN + q, kMN);
+  for (int v = 0; v < NA; ++v) {
+    const int vi = tid + 256 * v;
+    offAK[v] = lds_at(vi >> 2, kvK);
+    kAM[v] = vi / (BM / 8);
+    vAM[v] = (vi % (BM / 8)) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) offAM[v][q] = lds_at(vAM[v] + q, kAM[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < NB; ++v) {
+    const int vi = tid + 256 * v;
+    offBK[v] = lds_at(vi >> 2, kvK);
+    kBM[v] = vi / (BN / 8);
+    vBM[v] = (vi % (BN / 8)) * 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) offBM[v][q] = lds_at(vBM[v] + q, kBM[v]);
+  }
 
   // load cursor (product whose slabs are being loaded)
-  const u16* pa = nullptr;
-  const u16* pb = nullptr;
+  const u16* pa[NA];
+  const u16* pb[NB];
   long long stepA = 0, stepB = 0;
-  bool aK = true, bK = true, okA = false, okB = false;
-  int nvA = 8, nvB = 8;
+  bool aK = true, bK = true;
+  bool okA[NA], okB[NB];
+  int nvA[NA], nvB[NB];
   auto begin = [&](const RawTerm& T) {
     aK = !(T.flags & TF_TRANS_A);  // A stored m x k (k contiguous)
     bK = (T.flags & TF_TRANS_B);   // B stored n x k (k contiguous)
     const u16* A = (const u16*)T.A;
     const u16* B = (const u16*)T.B;
-    if (aK) {
-      okA = m0 + rK < J.m;
-      pa = A + (long long)(m0 + rK) * T.lda + kvK;
-      stepA = KT;
-    } else {
-      nvA = min(max(J.m - (m0 + vMN), 0), 8);
-      pa = A + (long long)kMN * T.lda + m0 + vMN;
-      stepA = (long long)KT * T.lda;
+#pragma unroll
+    for (int v = 0; v < NA; ++v) {
+      const int vi = tid + 256 * v;
+      if (aK) {
+        okA[v] = m0 + (vi >> 2) < J.m;
+        pa[v] = A + (long long)(m0 + (vi >> 2)) * T.lda + kvK;
+      } else {
+        nvA[v] = min(max(J.m - (m0 + vAM[v]), 0), 8);
+        pa[v] = A + (long long)kAM[v] * T.lda + m0 + vAM[v];
+      }
     }
-    if (bK) {
-      okB = n0 + rK < J.n;
-      pb = B + (long long)(n0 + rK) * T.ldb + kvK;
-      stepB = KT;
-    } else {
-      nvB = min(max(J.n - (n0 + vMN), 0), 8);
-      pb = B + (long long)kMN * T.ldb + n0 + vMN;
-      stepB = (long long)KT * T.ldb;
+    stepA = aK ? KT : (long long)KT * T.lda;
+#pragma unroll
+    for (int v = 0; v < NB; ++v) {
+      const int vi = tid + 256 * v;
+      if (bK) {
+        okB[v] = n0 + (vi >> 2) < J.n;
+        pb[v] = B + (long long)(n0 + (vi >> 2)) * T.ldb + kvK;
+      } else {
+        nvB[v] = min(max(J.n - (n0 + vBM[v]), 0), 8);
+        pb[v] = B + (long long)kBM[v] * T.ldb + n0 + vBM[v];
+      }
     }
+    stepB = bK ? KT : (long long)KT * T.ldb;
   };
-  uint4 ra, rb;
+  uint4 ra[NA], rb[NB];
   const uint4 z4 = make_uint4(0, 0, 0, 0);
   auto load = [&](int K, int k0) {
-    if (aK) {
-      const int nv = K - (k0 + kvK);
-      ra = (okA && nv > 0) ? *(const uint4*)pa : z4;
-      if (nv < 8) ra = keep_first<2>(ra, nv);
-    } else {
-      ra = (k0 + kMN < K && nvA > 0) ? *(const uint4*)pa : z4;
-      if (nvA < 8) ra = keep_first<2>(ra, nvA);
+    const int nvk = K - (k0 + kvK);  // valid k in this thread's vector ("K" role)
+#pragma unroll
+    for (int v = 0; v < NA; ++v) {
+      if (aK) {
+        ra[v] = (okA[v] && nvk > 0) ? *(const uint4*)pa[v] : z4;
+        if (nvk < 8) ra[v] = keep_first<2>(ra[v], nvk);
+      } else {
+        ra[v] = (k0 + kAM[v] < K && nvA[v] > 0) ? *(const uint4*)pa[v] : z4;
+        if (nvA[v] < 8) ra[v] = keep_first<2>(ra[v], nvA[v]);
+      }
+      pa[v] += stepA;
     }
-    if (bK) {
-      const int nv = K - (k0 + kvK);
-      rb = (okB && nv > 0) ? *(const uint4*)pb : z4;
-      if (nv < 8) rb = keep_first<2>(rb, nv);
-    } else {
-      rb = (k0 + kMN < K && nvB > 0) ? *(const uint4*)pb : z4;
-      if (nvB < 8) rb = keep_first<2>(rb, nvB);
+#pragma unroll
+    for (int v = 0; v < NB; ++v) {
+      if (bK) {
+        rb[v] = (okB[v] && nvk > 0) ? *(const uint4*)pb[v] : z4;
+        if (nvk < 8) rb[v] = keep_first<2>(rb[v], nvk);
+      } else {
+        rb[v] = (k0 + kBM[v] < K && nvB[v] > 0) ? *(const uint4*)pb[v] : z4;
+        if (nvB[v] < 8) rb[v] = keep_first<2>(rb[v], nvB[v]);
+      }
+      pb[v] += stepB;
     }
-    pa += stepA;
-    pb += stepB;
   };
   bool sK_A = true, sK_B = true;  // layout of the registers being stored
   auto store = [&](u16* sA, u16* sB) {
-    if (sK_A) {
-      *(uint4*)(sA + offK) = ra;
-    } else {
-      const unsigned w[4] = {ra.x, ra.y, ra.z, ra.w};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sA[offMN[q]] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+    for (int v = 0; v < NA; ++v) {
+      if (sK_A) {
+        *(uint4*)(sA + offAK[v]) = ra[v];
+      } else {
+        const unsigned w[4] = {ra[v].x, ra[v].y, ra[v].z, ra[v].w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sA[offAM[v][q]] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+      }
     }
-    if (sK_B) {
-      *(uint4*)(sB + offK) = rb;
-    } else {
-      const unsigned w[4] = {rb.x, rb.y, rb.z, rb.w};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sB[offMN[q]] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+    for (int v = 0; v < NB; ++v) {
+      if (sK_B) {
+        *(uint4*)(sB + offBK[v]) = rb[v];
+      } else {
+        const unsigned w[4] = {rb[v].x, rb[v].y, rb[v].z, rb[v].w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sB[offBM[v][q]] = (u16)(w[q >> 1] >> (16 * (q & 1)));
+      }
     }
   };
-  const int rdA0 = lds_at(wm + lr, 8 * lg), rdA1 = lds_at(wm + 16 + lr, 8 * lg);
-  const int rdB0 = lds_at(wn + lr, 8 * lg), rdB1 = lds_at(wn + 16 + lr, 8 * lg);
+  int rdA[FA], rdB[FB];
+#pragma unroll
+  for (int a = 0; a < FA; ++a) rdA[a] = lds_at(wm + a * 16 + lr, 8 * lg);
+#pragma unroll
+  for (int b = 0; b < FB; ++b) rdB[b] = lds_at(wn + b * 16 + lr, 8 * lg);
 
   auto next_dense = [&](int t) {
     while (t < W.tend && (terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) ++t;
@@ -655,8 +698,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
   }
   int buf = 0;
   while (t < W.tend) {
-    u16* sA = sm[buf][0];
-    u16* sB = sm[buf][1];
+    u16* sA = sA_[buf];
+    u16* sB = sB_[buf];
     store(sA, sB);
     __syncthreads();
     // next slab: same product, or the first slab of the next dense product
@@ -677,17 +720,20 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
       // product t starts: move the accumulator into its frame
       const float r = scale / alpha;
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] *= r;
+        for (int b = 0; b < FB; ++b) acc[a][b] *= r;
       scale = alpha;
     }
-    bf8 av0 = *(const bf8*)(sA + rdA0), av1 = *(const bf8*)(sA + rdA1);
-    bf8 bv0 = *(const bf8*)(sB + rdB0), bv1 = *(const bf8*)(sB + rdB1);
-    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bv0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bv1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, bv0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, bv1, acc[1][1], 0, 0, 0);
+    bf8 av[FA], bv[FB];
+#pragma unroll
+    for (int a = 0; a < FA; ++a) av[a] = *(const bf8*)(sA + rdA[a]);
+#pragma unroll
+    for (int b = 0; b < FB; ++b) bv[b] = *(const bf8*)(sB + rdB[b]);
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int b = 0; b < FB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
     sK_A = aK;
     sK_B = bK;
     buf ^= 1;
@@ -698,25 +744,25 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
   }
   if (scale != 1.f) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] *= scale;
+      for (int b = 0; b < FB; ++b) acc[a][b] *= scale;
   }
-  // write back (C, or the item's partial slot)
+  // write back (C, or the item's partial slot of BM x BN values)
   if (W.slot >= 0) {
-    float* P = (float*)part + (long long)W.slot * (TM * TN);
+    float* P = (float*)part + (long long)W.slot * (BM * BN);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < FB; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) P[(wm + a * 16 + 4 * lg + v) * TN + wn + b * 16 + lr] = acc[a][b][v];
+        for (int v = 0; v < 4; ++v) P[(wm + a * 16 + 4 * lg + v) * BN + wn + b * 16 + lr] = acc[a][b][v];
     return;
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < FB; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = m0 + wm + a * 16 + 4 * lg + v;
@@ -729,19 +775,21 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
       }
 }
 
-// Sum of the partial tiles of split items, in slot order, into C.
+// Sum of the partial tiles (bm x bn values each) of split items, in slot
+// order, into C.
 template <int MODE, int DC>
 __global__ __launch_bounds__(256) void reduce_kernel(const RawJob* __restrict__ jobs, const RedItem* __restrict__ items,
-                                                     const void* __restrict__ part) {
+                                                     const void* __restrict__ part, int bm, int bn) {
   using sc_t = typename std::conditional<MODE == DT_F64, double, float>::type;
   const RedItem R = items[blockIdx.x];
   const RawJob J = jobs[R.job];
-  const sc_t* P = (const sc_t*)part + (long long)R.slot0 * (TM * TN);
-  for (int e = threadIdx.x; e < TM * TN; e += 256) {
-    const int row = R.ti * TM + e / TN, col = R.tj * TN + e % TN;
+  const long long tile = (long long)bm * bn;
+  const sc_t* P = (const sc_t*)part + (long long)R.slot0 * tile;
+  for (int e = threadIdx.x; e < bm * bn; e += 256) {
+    const int row = R.ti * bm + e / bn, col = R.tj * bn + e % bn;
     if (row >= J.m || col >= J.n) continue;
     sc_t s = 0;
-    for (int q = 0; q < R.nslot; ++q) s += P[(long long)q * (TM * TN) + e];
+    for (int q = 0; q < R.nslot; ++q) s += P[(long long)q * tile + e];
     const long long o = (long long)row * J.ldc + col;
     if (J.accumulate) {
       if constexpr (DC == DT_F64) ((double*)J.C)[o] += (double)s;
@@ -1001,10 +1049,11 @@ struct Prepared {
   long long nitems = 0, nreds = 0, nslots = 0;
   int mode = DT_F64, da = DT_F64, db = DT_F64, dc = DT_F64, kt = 16;
   bool padded = false;  // BF16 launch served by gemm_bf16_padded
+  int bm = TM, bn = TN;  // output tile of the launch
 };
 
 using KernelFn = void (*)(const RawJob*, const RawTerm*, const WorkItem*, void*);
-using ReduceFn = void (*)(const RawJob*, const RedItem*, const void*);
+using ReduceFn = void (*)(const RawJob*, const RedItem*, const void*, int, int);
 
 KernelFn pick(int mode, int da, int db, int dc, int kt) {
   if (da != mode || db != mode) throw std::runtime_error("executor: operands must be stored in the arithmetic type");
@@ -1013,6 +1062,48 @@ KernelFn pick(int mode, int da, int db, int dc, int kt) {
   if (mode == DT_BF16 && dc == DT_BF16) return kt == 64 ? gemm_kernel<DT_BF16, DT_BF16, 64> : gemm_kernel<DT_BF16, DT_BF16, 32>;
   if (mode == DT_BF16 && dc == DT_F32) return kt == 64 ? gemm_kernel<DT_BF16, DT_F32, 64> : gemm_kernel<DT_BF16, DT_F32, 32>;
   throw std::runtime_error("executor: unsupported dtype combination");
+}
+
+KernelFn pick_padded(int dc, int bm, int bn) {
+#define P_(D, M, N) \
+  if (dc == D && bm == M && bn == N) return gemm_bf16_padded<D, M, N>;
+  P_(DT_BF16, 64, 64) P_(DT_BF16, 64, 128) P_(DT_BF16, 128, 64)
+  P_(DT_F32, 64, 64) P_(DT_F32, 64, 128) P_(DT_F32, 128, 64)
+#undef P_
+  throw std::runtime_error("executor: unsupported tile shape");
+}
+
+// Output tile of a padded BF16 launch.  Candidates 64x64, 64x128 and 128x64:
+// among those whose padded MFMA work (tiles x tile area x K rounded to 32)
+// is within 10 % of the smallest, the one with the fewest tiles (less fixed
+// cost per item, more reuse of each staged slab).  DMRG_TILE=MxN overrides.
+void choose_tile(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int& bm, int& bn) {
+  const int cand[3][2] = {{64, 64}, {64, 128}, {128, 64}};
+  if (const char* e = std::getenv("DMRG_TILE")) {
+    for (auto& c : cand)
+      if (std::string(e) == std::to_string(c[0]) + "x" + std::to_string(c[1])) {
+        bm = c[0];
+        bn = c[1];
+        return;
+      }
+  }
+  double work[3] = {0, 0, 0}, tiles[3] = {0, 0, 0};
+  for (const RawJob& J : jobs) {
+    double kpad = 0.0;
+    for (int64_t t = J.tbeg; t < J.tend; ++t)
+      if (!(terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) kpad += (double)((terms[t].k + 31) / 32 * 32);
+    for (int c = 0; c < 3; ++c) {
+      const double nt = (double)((J.m + cand[c][0] - 1) / cand[c][0]) * (double)((J.n + cand[c][1] - 1) / cand[c][1]);
+      tiles[c] += nt;
+      work[c] += nt * cand[c][0] * cand[c][1] * kpad;
+    }
+  }
+  const double wmin = std::min(work[0], std::min(work[1], work[2]));
+  int best = 0;
+  for (int c = 1; c < 3; ++c)
+    if (work[c] <= 1.1 * wmin && (work[best] > 1.1 * wmin || tiles[c] < tiles[best])) best = c;
+  bm = cand[best][0];
+  bn = cand[best][1];
 }
 
 // K slab of a BF16 launch: 64 when that pads the products' K by at most 1/8
@@ -1048,8 +1139,8 @@ ReduceFn pick_reduce(int mode, int dc) {
 // launch has at least ~16k items (enough to fill 256 CUs several times over)
 // but never below 64 steps.  Items are issued heaviest first (longest
 // processing time first), which bounds the tail of the launch.
-void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int kt, std::vector<WorkItem>& items,
-                std::vector<RedItem>& reds, long long& nslots) {
+void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int kt, int bm, int bn,
+                std::vector<WorkItem>& items, std::vector<RedItem>& reds, long long& nslots) {
   std::vector<double> pcost(terms.size());
   for (size_t t = 0; t < terms.size(); ++t)
     pcost[t] = (terms[t].flags & (TF_IDENT_A | TF_IDENT_B)) ? 0.5 : (double)((terms[t].k + kt - 1) / kt);
@@ -1057,7 +1148,7 @@ void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& ter
   for (const RawJob& J : jobs) {
     double c = 0.0;
     for (int64_t t = J.tbeg; t < J.tend; ++t) c += pcost[t];
-    total += c * (double)((J.m + TM - 1) / TM) * (double)((J.n + TN - 1) / TN);
+    total += c * (double)((J.m + bm - 1) / bm) * (double)((J.n + bn - 1) / bn);
   }
   double target = std::max(64.0, total / 16384.0);
   // DMRG_SPLIT_STEPS overrides the target (tuning and tests of the split path)
@@ -1087,7 +1178,7 @@ void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& ter
     }
     segs.push_back({(int)s0, (int)J.tend});
     scost.push_back(c);
-    const int tm = (J.m + TM - 1) / TM, tn = (J.n + TN - 1) / TN;
+    const int tm = (J.m + bm - 1) / bm, tn = (J.n + bn - 1) / bn;
     // per segment: first dense product and whether identities occur
     std::vector<int> d0(segs.size()), hid(segs.size());
     for (size_t q = 0; q < segs.size(); ++q) {
@@ -1242,11 +1333,12 @@ class HipExec : public Executor {
       P->padded = ok && !std::getenv("DMRG_NO_PADDED_KERNEL");
     }
     P->kt = P->padded ? 32 : (P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16);
+    if (P->padded) choose_tile(jobs, terms, P->bm, P->bn);
     pick(P->mode, da, db, dc, P->kt);  // validate
     if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
     std::vector<WorkItem> items;
     std::vector<RedItem> reds;
-    plan_items(jobs, terms, P->kt, items, reds, P->nslots);
+    plan_items(jobs, terms, P->kt, P->bm, P->bn, items, reds, P->nslots);
     P->nitems = (long long)items.size();
     if (P->nitems > 0x7fffffffLL) throw std::runtime_error("executor: too many work items in one launch");
     P->nreds = (long long)reds.size();
@@ -1263,7 +1355,7 @@ class HipExec : public Executor {
         upload(P->d_reds, reds.data(), reds.size() * sizeof(RedItem));
       }
     }
-    const size_t need = (size_t)P->nslots * TM * TN * (P->mode == DT_F64 ? 8 : 4);
+    const size_t need = (size_t)P->nslots * P->bm * P->bn * (P->mode == DT_F64 ? 8 : 4);
     if (need > part_bytes_) {
       sync();
       if (part_) release(part_);
@@ -1277,8 +1369,7 @@ class HipExec : public Executor {
   void run(void* h) override {
     auto* P = (Prepared*)h;
     if (!P->nitems) return;
-    KernelFn k = P->padded ? (P->dc == DT_BF16 ? gemm_bf16_padded<DT_BF16> : gemm_bf16_padded<DT_F32>)
-                           : pick(P->mode, P->da, P->db, P->dc, P->kt);
+    KernelFn k = P->padded ? pick_padded(P->dc, P->bm, P->bn) : pick(P->mode, P->da, P->db, P->dc, P->kt);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing_) {
       HIP_OK(hipEventCreate(&e0));
@@ -1293,7 +1384,7 @@ class HipExec : public Executor {
       ReduceFn r = pick_reduce(P->mode, P->dc);
       for (long long t0 = 0; t0 < P->nreds; t0 += maxg) {
         const long long nt = std::min(maxg, P->nreds - t0);
-        hipLaunchKernelGGL(r, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_reds + t0, part_);
+        hipLaunchKernelGGL(r, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_reds + t0, part_, P->bm, P->bn);
       }
       HIP_OK(hipGetLastError());
     }
