@@ -77,7 +77,7 @@ def cpu_baseline(lib_flops_fn):
                       f"{reps} reps after 1 warm-up, {dt * 1e3:.0f} ms each"}
 
 
-def accuracy_case(DMRG, BF16, FP64):
+def accuracy_case(DMRG, BF16, FP64, jd_inner):
     """Mixed precision against the FP64 path where both Davidson runs converge
     to the paper's residual (1e-7): the centre two-site block of CAS(10,10),
     S=0, D=1000 (complete two-site space, 19,404 coefficients), same start
@@ -89,7 +89,7 @@ def accuracy_case(DMRG, BF16, FP64):
     psi, _ = random_psi(mps, seed=22)
     out = {}
     for name, prec in (("bf16+fp64", BF16), ("fp64", FP64)):
-        d = DMRG(h, g, 10, 0, hpsi_prec=prec, davidson_max_iter=400)
+        d = DMRG(h, g, 10, 0, hpsi_prec=prec, davidson_max_iter=400, davidson_jd_inner=jd_inner)
         b, c = mps.bond_table()
         d.set_mps(4, b, c, mps.site_blocks_flat())
         r = d.davidson(psi)
@@ -101,6 +101,8 @@ def accuracy_case(DMRG, BF16, FP64):
             "resid_mixed": out["bf16+fp64"]["resid"], "resid_fp64": out["fp64"]["resid"],
             "matvecs_mixed": {"bf16": out["bf16+fp64"]["n_lo"], "fp64": out["bf16+fp64"]["n_fp64"]},
             "matvecs_fp64": out["fp64"]["n_fp64"],
+            "refinement": f"Jacobi-Davidson, {jd_inner} low-precision CG steps per correction" if jd_inner
+            else "Davidson restarted in FP64",
             "converged": bool(out["bf16+fp64"]["converged"] and out["fp64"]["converged"])}
 
 
@@ -115,6 +117,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true", help="skip the converged mixed-vs-FP64 case")
     ap.add_argument("--dav-lo", type=int, default=8, help="BF16 Davidson iterations in the DMRG step")
     ap.add_argument("--dav-hi", type=int, default=3, help="FP64 refinement iterations in the DMRG step")
+    ap.add_argument("--jd-inner", type=int, default=10,
+                    help="CG steps of the Jacobi-Davidson refinement (0: plain FP64 Davidson refinement)")
     ap.add_argument("--x-budget", type=int, default=0, metavar="ELEMS",
                     help="cap on the X intermediates of one H*psi chunk (elements; 0: library default)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -144,7 +148,7 @@ def main():
     psi, lay = random_psi(mps, seed=w["seed"] + 1)
     log(f"{w['name']}: MPS drawn in {time.perf_counter() - t0:.1f}s, psi has {psi.size} coefficients")
     dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=BF16, davidson_max_iter=args.dav_lo,
-              davidson_refine_iter=args.dav_hi, work_budget_elems=args.x_budget)
+              davidson_refine_iter=args.dav_hi, work_budget_elems=args.x_budget, davidson_jd_inner=args.jd_inner)
     bs, cnt = mps.bond_table()
     t0 = time.perf_counter()
     dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())
@@ -219,7 +223,7 @@ def main():
         step = {"seconds": t2 - t0, "davidson_s": t1 - t0, "truncate_and_grow_s": t2 - t1,
                 "matvecs": {"bf16": r["n_lo"], "fp64": r["n_fp64"]}, "energy_Eh": r["energy"],
                 "residual": r["resid"], "residual_target": 1e-7, "converged": r["converged"],
-                "budget": {"bf16_iters": args.dav_lo, "fp64_iters": args.dav_hi},
+                "budget": {"bf16_iters": args.dav_lo, "fp64_iters": args.dav_hi, "jd_inner_cg": args.jd_inner},
                 "trunc_err": err, "d_kept": kept,
                 "start_vector": "random (no previous step to warm-start from)"}
         log(f"DMRG step: {step['seconds']:.1f}s (Davidson {step['davidson_s']:.1f}s, "
@@ -228,7 +232,7 @@ def main():
     acc = None
     if not args.no_accuracy:
         log("converged mixed-vs-FP64 case")
-        acc = accuracy_case(DMRG, BF16, FP64)
+        acc = accuracy_case(DMRG, BF16, FP64, args.jd_inner)
 
     base = None
     if not args.no_cpu_baseline:

@@ -76,6 +76,13 @@ typedef struct {
                                   the two-site block (memory grows with n)        */
   int davidson_refine_iter;    /* iterations of the FP64 refinement phase when
                                   hpsi_prec is not FP64; 0: davidson_max_iter     */
+  int davidson_jd_inner;       /* refinement with hpsi_prec not FP64: 0 expands the
+                                  basis with the diagonally preconditioned residual;
+                                  k > 0 with the Jacobi-Davidson correction from k
+                                  conjugate-gradient steps whose matvecs use
+                                  hpsi_prec                                        */
+  int davidson_lowprec_iter;   /* iterations of the low-precision Davidson phase
+                                  before refinement; -1: davidson_max_iter, 0: none */
 } dmrg_opts;
 
 /* Create a context; copies h (n*n) and g (n^4).  Errors: ARG, SYMMETRY
@@ -111,8 +118,11 @@ int dmrg_heff_diag(dmrg_ctx *c, int k, double *diag);
 /* Davidson for the lowest eigenpair of H_eff at block (k, k+1), starting from
  * psi_inout (host, n_elems; a zero vector selects a random start).  Bulk
  * matvecs in opts.hpsi_prec, residuals and Rayleigh-Ritz in FP64 with FP64
- * correction matvecs.  On return psi_inout holds the normalised eigenvector,
- * energy the eigenvalue plus e_core, resid_norm ||H x - E x||_2.
+ * correction matvecs (with opts.davidson_jd_inner > 0, Jacobi-Davidson
+ * refinement whose correction equations are solved with hpsi_prec matvecs).
+ * On return psi_inout holds the normalised eigenvector, energy the
+ * eigenvalue plus e_core, resid_norm ||H x - E x||_2; n_matvec_lowprec counts
+ * every hpsi_prec matvec (inner solves included), n_matvec_fp64 the FP64 ones.
  * Returns NOCONV (outputs still written) if tol is not reached. */
 int dmrg_davidson_step(dmrg_ctx *c, int k, double *psi_inout, double *energy, double *resid_norm,
                        int *n_matvec_lowprec, int *n_matvec_fp64);

@@ -45,7 +45,8 @@ extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, 
   if (o->two_s < 0 || ((o->n_elec + o->two_s) & 1) || o->two_s > std::min(o->n_elec, 2 * n - o->n_elec))
     return fail(DMRG_ERR_SYMMETRY, "dmrg_create: 2S incompatible with N");
   if (o->hpsi_prec < 0 || o->hpsi_prec > 2) return fail(DMRG_ERR_ARG, "dmrg_create: bad hpsi_prec");
-  if (o->davidson_max_iter < 0 || o->davidson_refine_iter < 0 || o->davidson_max_subspace < 0)
+  if (o->davidson_max_iter < 0 || o->davidson_refine_iter < 0 || o->davidson_max_subspace < 0 ||
+      o->davidson_jd_inner < 0 || o->davidson_lowprec_iter < -1)
     return fail(DMRG_ERR_ARG, "dmrg_create: negative Davidson budget");
   const size_t n2 = (size_t)n * n, n4 = n2 * n2;
   if (!finite_all(h, n2) || !finite_all(g, n4)) return fail(DMRG_ERR_NONFINITE, "dmrg_create: non-finite integral");

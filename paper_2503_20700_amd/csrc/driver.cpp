@@ -5,10 +5,16 @@
 // bulk matvec (FP32 or BF16 operands, FP32 accumulation) the iteration runs
 // in two phases: (1) Davidson with low-precision matvecs until the residual
 // reaches the precision's noise floor, (2) FP64 refinement: Davidson
-// restarted from the phase-1 Ritz vector with FP64 matvecs until tol.  All
-// vectors, projections (dot products), orthogonalisation and residuals are
-// FP64 on the GPU; only the small projected matrix (<= 32 x 32) is
-// diagonalised on the host.
+// restarted from the phase-1 Ritz vector with FP64 matvecs until tol.  In
+// the refinement the basis images, Ritz pairs and residuals are FP64, and
+// each new basis vector is, with davidson_jd_inner = k > 0, the Jacobi-
+// Davidson correction: k conjugate-gradient steps on
+//     (I - x x^T)(H - theta)(I - x x^T) t = -r,   t orthogonal to x,
+// whose matvecs use the low precision.  The FP64 matvecs then only measure
+// the residual of each refined vector, and their count drops to a few
+// (iterative refinement of the eigenpair).  All vectors, projections (dot
+// products), orthogonalisation and residuals are FP64 on the GPU; only the
+// small projected matrix (<= 48 x 48) is diagonalised on the host.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -76,7 +82,7 @@ void jacobi_eig(int m, std::vector<double> A, std::vector<double>& w, std::vecto
 }
 
 struct Workspace {
-  int bV = -1, bW = -1, bx = -1, bhx = -1, br = -1, bt = -1;
+  int bV = -1, bW = -1, bx = -1, bhx = -1, br = -1, bt = -1, bp = -1, bq = -1, bs = -1;
   int64_t n = 0;
   int mmax = 0;
 };
@@ -94,12 +100,61 @@ void matvec(dmrg_ctx* c, const double* x, double* y, int prec, int64_t n) {
 
 struct PhaseResult {
   double theta = 0.0, resid = 0.0;
-  int matvecs = 0;
+  int matvecs = 0;       // matvecs in the phase's own precision
+  int inner_matvecs = 0;  // low-precision matvecs of the correction solves
   bool converged = false;
 };
 
+double dot(Executor* ex, const double* a, const double* b, int64_t n) {
+  double v = 0.0;
+  ex->multidot(a, n, 1, b, n, &v);
+  return v;
+}
+
+// Jacobi-Davidson correction: approximately solve
+//   (I - x x^T)(H_lo - theta)(I - x x^T) t = -r,  t orthogonal to x,
+// with at most `steps` conjugate-gradient iterations (H_lo: matvecs in
+// precision lo_prec).  Returns the matvecs used; t = 0 if none succeeded.
+int jd_correction(dmrg_ctx* c, const Workspace& ws, int lo_prec, double theta, int steps) {
+  Executor* ex = c->ex.get();
+  const int64_t n = ws.n;
+  double* x = P(c, ws.bx);
+  double* r = P(c, ws.br);
+  double* t = P(c, ws.bt);
+  double* p = P(c, ws.bp);
+  double* q = P(c, ws.bq);
+  double* res = P(c, ws.bs);
+  auto project = [&](double* v) {  // v -= x (x.v)
+    const double a = dot(ex, x, v, n);
+    ex->axpby(v, 1.0, v, -a, x, n);
+  };
+  ex->axpby(t, 0.0, r, 0.0, r, n);   // t = 0
+  ex->axpby(res, -1.0, r, 0.0, r, n);  // res = -r
+  project(res);
+  ex->copy_d2d(p, res, (size_t)n * 8);
+  double rr = dot(ex, res, res, n);
+  const double rr0 = rr;
+  int used = 0;
+  for (int j = 0; j < steps && rr > 1e-30 * std::max(rr0, 1e-300); ++j) {
+    matvec(c, p, q, lo_prec, n);
+    ++used;
+    ex->axpby(q, 1.0, q, -theta, p, n);
+    project(q);
+    const double pq = dot(ex, p, q, n);
+    if (!(pq > 0.0)) break;  // the projected operator is not positive on p
+    const double a = rr / pq;
+    ex->axpby(t, 1.0, t, a, p, n);
+    ex->axpby(res, 1.0, res, -a, q, n);
+    const double rr2 = dot(ex, res, res, n);
+    ex->axpby(p, 1.0, res, rr2 / rr, p, n);
+    rr = rr2;
+  }
+  return used;
+}
+
 // Davidson on the device basis V (rows), W = H V; starts from x (normalised).
-PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int max_iter) {
+PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int max_iter, int jd_steps = 0,
+                           int jd_prec = DMRG_FP64) {
   Executor* ex = c->ex.get();
   const int64_t n = ws.n;
   const int mmax = ws.mmax;
@@ -161,8 +216,15 @@ PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int
       m = keep;
       ex->axpby(r, 1.0, hx, -theta, x, n);
     }
-    // correction t = (theta - D)^-1 r, orthogonalised against V twice
-    ex->precond(t, r, diag, theta, 1e-8, n);
+    // new direction: Jacobi-Davidson correction (low-precision inner solve)
+    // or the diagonally preconditioned residual t = (theta - D)^-1 r;
+    // orthogonalised against V twice
+    bool have_t = false;
+    if (jd_steps > 0) {
+      res.inner_matvecs += jd_correction(c, ws, jd_prec, theta, jd_steps);
+      have_t = dot(ex, t, t, n) > 0.0;
+    }
+    if (!have_t) ex->precond(t, r, diag, theta, 1e-8, n);
     for (int pass = 0; pass < 2; ++pass) {
       ex->multidot(V, n, m, t, n, tmp.data());
       for (int i = 0; i < m; ++i) tmp[i] = -tmp[i];
@@ -200,7 +262,8 @@ Workspace workspace(dmrg_ctx* c, int64_t n, int mmax) {
   if (c->work_bufs.empty() || c->work_n != n || c->work_mmax != mmax) {
     for (int b : c->work_bufs) c->C->free_buf(b);
     c->work_bufs = {c->C->new_buf((int64_t)(mmax + kKeep) * n), c->C->new_buf((int64_t)(mmax + kKeep) * n), c->C->new_buf(n),
-                    c->C->new_buf(n), c->C->new_buf(n), c->C->new_buf(n)};
+                    c->C->new_buf(n), c->C->new_buf(n), c->C->new_buf(n), c->C->new_buf(n), c->C->new_buf(n),
+                    c->C->new_buf(n)};
     c->work_n = n;
     c->work_mmax = mmax;
   }
@@ -213,6 +276,9 @@ Workspace workspace(dmrg_ctx* c, int64_t n, int mmax) {
   ws.bhx = c->work_bufs[3];
   ws.br = c->work_bufs[4];
   ws.bt = c->work_bufs[5];
+  ws.bp = c->work_bufs[6];
+  ws.bq = c->work_bufs[7];
+  ws.bs = c->work_bufs[8];
   return ws;
 }
 }  // namespace
@@ -248,17 +314,21 @@ extern "C" int dmrg_davidson_step(dmrg_ctx* c, int k, double* psi, double* energ
     const int prec = c->opts.hpsi_prec;
     int lo = 0, hi = 0;
     PhaseResult pr;
-    if (prec != DMRG_FP64) {
+    const int lo_iter = c->opts.davidson_lowprec_iter < 0 ? max_iter : c->opts.davidson_lowprec_iter;
+    if (prec != DMRG_FP64 && lo_iter > 0) {
       // phase 1: low-precision matvecs down to the precision's noise floor
       const double floor_tol = (prec == DMRG_BF16) ? 3e-3 : 1e-5;
-      pr = davidson_phase(c, ws, prec, std::max(tol, floor_tol), max_iter);
+      pr = davidson_phase(c, ws, prec, std::max(tol, floor_tol), lo_iter);
       lo = pr.matvecs;
     }
-    // phase 2 (or the whole solve for FP64): FP64 matvecs to tol
+    // phase 2 (or the whole solve for FP64): FP64 matvecs to tol, with
+    // Jacobi-Davidson corrections from low-precision inner solves if asked
     const int refine_iter =
         (prec != DMRG_FP64 && c->opts.davidson_refine_iter > 0) ? c->opts.davidson_refine_iter : max_iter;
-    pr = davidson_phase(c, ws, DMRG_FP64, tol, refine_iter);
+    const int jd = prec != DMRG_FP64 ? c->opts.davidson_jd_inner : 0;
+    pr = davidson_phase(c, ws, DMRG_FP64, tol, refine_iter, jd, prec);
     hi = pr.matvecs;
+    lo += pr.inner_matvecs;
     c->ex->download(psi, c->C->ptr(ws.bx), (size_t)n * 8);
     *energy = pr.theta + c->opts.e_core;
     *resid = pr.resid;

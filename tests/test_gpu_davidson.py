@@ -36,3 +36,29 @@ def test_davidson_lowest_eigenvalue(prec, case):
     assert np.linalg.norm(hd @ x - exact * x) < 1e-6
     if prec != 0:
         assert r["n_lo"] > 0
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16"])
+@pytest.mark.parametrize("lowprec_iter", [-1, 0], ids=["phase1", "jd-only"])
+@pytest.mark.parametrize("case", [(8, 8, 0, 64, 3, 0), (7, 7, 1, 16, 2, 3)], ids=["cas88_s0", "cas77_s1/2"])
+def test_davidson_jacobi_davidson_refinement(prec, lowprec_iter, case):
+    # Refinement by Jacobi-Davidson corrections from low-precision inner CG:
+    # same eigenpair as the dense FP64 eigensolver at the paper's residual,
+    # with few FP64 matvecs.
+    from paper_2503_20700_amd.binding import DMRG
+    n, ne, ts, d, k, seed = case
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    dm = DMRG(h, g, ne, ts, hpsi_prec=prec, davidson_tol=1e-7, davidson_max_iter=200, davidson_max_subspace=24,
+              davidson_jd_inner=10, davidson_lowprec_iter=lowprec_iter)
+    bs, cnt = mps.bond_table()
+    dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+    r = dm.davidson(psi)
+    print(f"[jd] prec={prec} phase1={lowprec_iter} case={case}: lo={r['n_lo']} fp64={r['n_fp64']}", flush=True)
+    assert r["converged"], r
+    hd = heff.HeffDefinition(h, g, mps, lay).dense()
+    exact = np.linalg.eigvalsh(0.5 * (hd + hd.T))[0]
+    assert abs(r["energy"] - exact) <= 1e-6
+    assert np.linalg.norm(hd @ r["psi"] - exact * r["psi"]) < 1e-6
+    assert r["n_lo"] > 0
