@@ -525,8 +525,11 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
   constexpr int KT = 32, LS = KT + 8;     // LDS row stride in bf16 elements (80 bytes)
   constexpr int NA = BM / 64, NB = BN / 64;  // 16-byte vectors per thread per slab
   constexpr int FA = BM / 32, FB = BN / 32;  // 16x16 MFMA blocks per wave along m / n
-  __shared__ __attribute__((aligned(16))) u16 sA_[2][BM * LS];
-  __shared__ __attribute__((aligned(16))) u16 sB_[2][BN * LS];
+  // two A and two B slab buffers; after the K loop the same memory stages
+  // a BF16 output tile (BM x BN <= 2 (BM + BN) LS elements)
+  __shared__ __attribute__((aligned(16))) u16 smem[2 * (BM + BN) * LS];
+  static_assert(BM * BN <= 2 * (BM + BN) * LS, "output tile must fit the slab buffers");
+  // buffer b: A slab at smem + b * BM * LS, B slab at smem + (2 BM + b BN) * LS
   const int tid = threadIdx.x;
   const WorkItem W = items[blockIdx.x];
   const RawJob J = jobs[W.job];
@@ -698,8 +701,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
   }
   int buf = 0;
   while (t < W.tend) {
-    u16* sA = sA_[buf];
-    u16* sB = sB_[buf];
+    u16* sA = smem + buf * (BM * LS);
+    u16* sB = smem + (2 * BM + buf * BN) * LS;
     store(sA, sB);
     __syncthreads();
     // next slab: same product, or the first slab of the next dense product
@@ -749,6 +752,28 @@ __global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict
       for (int b = 0; b < FB; ++b) acc[a][b] *= scale;
   }
   // write back (C, or the item's partial slot of BM x BN values)
+  if constexpr (DC == DT_BF16) {
+    // BF16 output with 16-byte aligned rows of a multiple of 8 columns
+    // (the X intermediates): stage the tile in LDS, store 16-byte vectors
+    if (W.slot < 0 && !J.accumulate && (((uintptr_t)J.C) & 15) == 0 && (J.ldc & 7) == 0 && (J.n & 7) == 0) {
+      __syncthreads();  // every wave is done reading the last slab
+#pragma unroll
+      for (int a = 0; a < FA; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) smem[(wm + a * 16 + 4 * lg + v) * BN + wn + b * 16 + lr] = f2bf(acc[a][b][v]);
+      __syncthreads();
+      constexpr int VPR = BN / 8;  // vectors per tile row
+#pragma unroll
+      for (int i = tid; i < BM * VPR; i += 256) {
+        const int r = i / VPR, c8 = (i % VPR) * 8;
+        if (m0 + r < J.m && n0 + c8 < J.n)
+          *(uint4*)((u16*)J.C + (long long)(m0 + r) * J.ldc + n0 + c8) = *(const uint4*)(smem + r * BN + c8);
+      }
+      return;
+    }
+  }
   if (W.slot >= 0) {
     float* P = (float*)part + (long long)W.slot * (BM * BN);
 #pragma unroll
