@@ -42,6 +42,25 @@ def workload(name):
     raise SystemExit(f"unknown config {name}")
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_bf16_padded_cas82_d4096.json")
+
+
+def measured_traffic(config):
+    """HBM bytes of the dominant kernel per BF16 H*psi, from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the CAS(82,82) workload,
+    or None if there is none or the kernel source changed since."""
+    if config != "cfg4" or not os.path.exists(TRAFFIC_FILE):
+        return None, None
+    from paper_2503_20700_amd.rocprof_summary import source_sha256
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != source_sha256():
+        return None, None
+    return t["hbm_bytes_per_hpsi"], {"fetch_bytes": t["fetch"]["hbm_bytes_last_hpsi"],
+                                     "write_bytes": t["write"]["hbm_bytes_last_hpsi"],
+                                     "launches": t["launches"], "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -246,6 +265,9 @@ def main():
         log("timing the oracle on its bounded sample")
         base = cpu_baseline(fl)
 
+    traffic, traffic_detail = measured_traffic(args.config)
+    if traffic is not None:
+        traffic_detail["hbm_gb_per_s"] = traffic / (k_lo / K * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": lo_tflops,
@@ -262,7 +284,8 @@ def main():
         "config": {"workload": w["name"], "n_orb": w["n"], "n_elec": w["N"], "two_s": w["two_s"], "D": w["D"],
                    "two_site_block": [w["k"], w["k"] + 1], "psi_len": int(psi.size)},
         "roofline": {"bound": "mfma", "achieved": lo_kernel_tflops, "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                     "frac": lo_kernel_tflops / PEAK["bf16"], "traffic": None},
+                     "frac": lo_kernel_tflops / PEAK["bf16"], "traffic": traffic},
+        "traffic_detail": traffic_detail,
         "cpu_baseline": base,
         "hpsi_flops": flops,
         "bf16": {"ms_per_hpsi": t_lo / K * 1e3, "kernel_ms_per_hpsi": k_lo / K, "launches_per_hpsi": n_lo // K},
