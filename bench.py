@@ -42,6 +42,24 @@ def workload(name):
     raise SystemExit(f"unknown config {name}")
 
 
+def batch_instances(count=48, master_seed=2):
+    """The batched workload: `count` independent centre two-site blocks.
+    Instance i: n_i uniform on {10..24}, N_i = n_i, 2S_i = n_i mod 2 (doublets
+    for odd n), D_i uniform on {64, 128, 256, 512} multiplets (capped by the
+    exact sector ranks), integrals by the small-CAS recipe at size n_i with
+    4 n_i auxiliary vectors, seed 1000 + i."""
+    from synth.integrals import small_cas
+    rng = np.random.default_rng(master_seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(10, 25))
+        d = int(rng.choice([64, 128, 256, 512]))
+        seed = 1000 + i
+        h, g, _ = small_cas(n, seed, naux=4 * n)
+        out.append(dict(n=n, N=n, two_s=n % 2, D=d, k=n // 2 - 1, h=h, g=g, seed=seed))
+    return out
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_bf16_padded_cas82_d4096.json")
 
 
@@ -146,6 +164,9 @@ def main():
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.config == "batch48":
+        batch_main(args)
+        return
 
     import torch
     from paper_2503_20700_amd.binding import BF16, DMRG, FP64
@@ -303,6 +324,109 @@ def main():
         "peak_device_bytes": st["peak_bytes"],
     }
     print(json.dumps(out), flush=True)
+
+
+def batch_main(args):
+    """48 independent instances: H*psi of all of them one after another (one
+    dmrg_hpsi_dev per instance) against one batched call (dmrg_batch_hpsi: one
+    grouped launch per stage for all 48), in BF16 and FP64."""
+    import torch
+    from paper_2503_20700_amd.binding import BF16, DMRG, FP64, HpsiBatch
+    from synth.mps import random_mps, random_psi
+
+    dev = torch.device("cuda:0")
+    insts = batch_instances()
+    t0 = time.perf_counter()
+    dms, xs, flops = [], [], []
+    for w in insts:
+        mps = random_mps(w["n"], w["N"], w["two_s"], w["D"], k=w["k"], seed=w["seed"])
+        psi, _ = random_psi(mps, seed=w["seed"] + 1)
+        dm = DMRG(w["h"], w["g"], w["N"], w["two_s"])
+        bs, cnt = mps.bond_table()
+        dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())
+        _, f = dm.hpsi(psi, FP64)  # plans the task lists
+        dms.append(dm)
+        xs.append(torch.from_numpy(psi).to(dev))
+        flops.append(f)
+        w["psi_len"] = int(psi.size)
+    t_setup = time.perf_counter() - t0
+    total_flops = float(sum(flops))
+    log(f"{len(insts)} instances set up in {t_setup:.1f}s: psi lengths {min(w['psi_len'] for w in insts)}.."
+        f"{max(w['psi_len'] for w in insts)}, {total_flops:.3e} flop per round of H*psi")
+    ys_seq = [torch.empty_like(x) for x in xs]
+    ys_bat = [torch.empty_like(x) for x in xs]
+    ptr_in = [x.data_ptr() for x in xs]
+    ptr_seq = [y.data_ptr() for y in ys_seq]
+    ptr_bat = [y.data_ptr() for y in ys_bat]
+    K = max(args.steps, 1)
+    res = {}
+    for name, prec in (("bf16", BF16), ("fp64", FP64)):
+        def seq():
+            for dm, a, b in zip(dms, ptr_in, ptr_seq):
+                dm.hpsi_dev(a, b, prec)
+            torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch = HpsiBatch(dms, prec)
+        t_make = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            seq()
+            batch.run(ptr_in, ptr_bat)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            seq()
+        t_seq = (time.perf_counter() - t0) / K
+        dms[0].kernel_timing(1)
+        t0 = time.perf_counter()
+        for _ in range(K):
+            batch.run(ptr_in, ptr_bat)
+        torch.cuda.synchronize()
+        t_bat = (time.perf_counter() - t0) / K
+        k_ms, launches = dms[0].kernel_timing(0)
+        diff = max(float((yb - ys).abs().max() / ys.abs().max()) for yb, ys in zip(ys_bat, ys_seq))
+        res[name] = {"ms_batched": t_bat * 1e3, "ms_one_by_one": t_seq * 1e3, "speedup": t_seq / t_bat,
+                     "tflops_batched": total_flops / t_bat / 1e12, "tflops_one_by_one": total_flops / t_seq / 1e12,
+                     "kernel_ms_batched": k_ms / K, "launches_batched": launches // K,
+                     "kernel_tflops_batched": total_flops / (k_ms / K * 1e-3) / 1e12 if k_ms > 0 else None,
+                     "batch_create_s": t_make, "max_rel_diff_batched_vs_one_by_one": diff}
+        log(f"{name}: batched {t_bat * 1e3:.2f} ms, one by one {t_seq * 1e3:.2f} ms per round of "
+            f"{len(insts)} H*psi; max rel diff {diff:.2e}")
+        batch.close()
+    # property that holds at any size: <phi|H psi> = <H phi|psi> per instance (FP64, batched)
+    herm = 0.0
+    batch = HpsiBatch(dms, FP64)
+    rng = np.random.default_rng(9)
+    phis = [torch.from_numpy(rng.normal(size=x.numel())).to(dev) for x in xs]
+    hphis = [torch.empty_like(p) for p in phis]
+    batch.run(ptr_in, ptr_bat)
+    batch.run([p.data_ptr() for p in phis], [q.data_ptr() for q in hphis])
+    torch.cuda.synchronize()
+    for x, y, p, q in zip(xs, ys_bat, phis, hphis):
+        herm = max(herm, float(abs(p @ y - q @ x) / (p.norm() * y.norm())))
+    batch.close()
+    b16 = res["bf16"]
+    kt = b16["kernel_tflops_batched"]
+    out = {
+        "metric": "batched H·ψ TFLOP/s, 48 independent instances in one grouped launch per stage",
+        "value": b16["tflops_batched"],
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": b16["ms_batched"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "48 instances: CAS(n,n) with n uniform on 10..24, 2S = n mod 2, D uniform on "
+                               "{64,128,256,512}, centre two-site block, small-CAS integrals (naux = 4n)",
+                   "instances": [[w["n"], w["two_s"], w["D"], w["psi_len"]] for w in insts]},
+        "roofline": {"bound": "mfma", "achieved": kt, "peak": PEAK["bf16"], "unit": "TFLOP/s",
+                     "frac": kt / PEAK["bf16"] if kt else None, "traffic": None},
+        "cpu_baseline": None,
+        "flops_per_round": total_flops,
+        "bf16": b16, "fp64": res["fp64"],
+        "fp64_hermiticity_rel_max": herm,
+        "setup_s": t_setup,
+    }
+    print(json.dumps(out), flush=True)
+    for dm in dms:
+        dm.close()
 
 
 if __name__ == "__main__":

@@ -175,6 +175,26 @@ int dmrg_kernel_timing(dmrg_ctx *c, int mode, double *ms, long long *launches);
 int dmrg_gemm_selftest(int m, int n, int k, const double *A, int trans_a, int ident_a, const double *B,
                        int trans_b, int ident_b, double alpha, double beta, double *C, int prec);
 
+/* Batched H*psi over independent contexts (Sec. "Numerical procedure" runs
+ * the same H_eff psi product in every Davidson iteration of every instance;
+ * many small instances -- different molecules, geometries or spin states --
+ * fill the GPU together where one alone cannot).  dmrg_batch_create takes
+ * `count` distinct contexts, each with an MPS loaded (dmrg_set_mps), builds
+ * each one's H*psi plan at its current two-site block if needed, and merges
+ * the block-product tasks of all of them into one grouped launch per stage
+ * and chunk, run on the first context's stream.  prec as in dmrg_hpsi.
+ * The contexts must outlive the batch; a context whose block changes after
+ * the batch was made (dmrg_set_mps, dmrg_truncate) makes dmrg_batch_hpsi fail
+ * with ARG.  dmrg_batch_hpsi: d_in[i] / d_out[i] are device FP64 buffers of
+ * context i's n_elems (dmrg_psi_layout); the result equals dmrg_hpsi_dev on
+ * each context with the same prec (FP64: up to summation order within a
+ * split-K reduction, which is fixed by the merged plan).  Errors: ARG, BUDGET,
+ * HIP. */
+typedef struct dmrg_batch dmrg_batch;
+int dmrg_batch_create(dmrg_ctx *const *ctxs, int count, int prec, dmrg_batch **out);
+int dmrg_batch_hpsi(dmrg_batch *b, const void *const *d_in, void *const *d_out);
+void dmrg_batch_destroy(dmrg_batch *b);
+
 const char *dmrg_last_error(void);
 void dmrg_destroy(dmrg_ctx *c);
 

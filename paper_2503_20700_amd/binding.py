@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+import weakref
 
 import numpy as np
 
@@ -45,6 +46,14 @@ def load(path=None):
         return _LIBS[path]
     if not os.path.exists(path):
         raise FileNotFoundError(f"native library not built: {path} (run __graft_entry__.build())")
+    # PyTorch-ROCm ships its own HIP runtime.  If the library's runtime is
+    # loaded into the process first, torch's later finds no GPU; loaded in
+    # this order both see it, so callers may hand torch device buffers to
+    # the *_dev entry points.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ct.CDLL(path)
     P, I, D, LL, V = ct.c_void_p, ct.c_int, ct.c_double, ct.c_longlong, None
     dp = ct.POINTER(ct.c_double)
@@ -66,6 +75,9 @@ def load(path=None):
         "dmrg_current_block": (I, [P, ip]),
         "dmrg_get_bond": (I, [P, I, ip, ip]),
         "dmrg_get_site": (I, [P, I, dp, llp]),
+        "dmrg_batch_create": (I, [ct.POINTER(P), I, I, ct.POINTER(P)]),
+        "dmrg_batch_hpsi": (I, [P, ct.POINTER(P), ct.POINTER(P)]),
+        "dmrg_batch_destroy": (V, [P]),
         "dmrg_last_error": (ct.c_char_p, []),
         "dmrg_destroy": (V, [P]),
     }
@@ -80,8 +92,8 @@ def load(path=None):
 def exported_symbols():
     return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_heff_diag",
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
-            "dmrg_kernel_timing", "dmrg_current_block", "dmrg_get_bond", "dmrg_get_site", "dmrg_last_error",
-            "dmrg_destroy"]
+            "dmrg_kernel_timing", "dmrg_current_block", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
+            "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_last_error", "dmrg_destroy"]
 
 
 def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ident_b=False, alpha=1.0, beta=0.0,
@@ -130,6 +142,7 @@ class DMRG:
                          hpsi_prec, work_budget_elems, int(keep_blocks), davidson_refine_iter,
                          davidson_jd_inner, davidson_lowprec_iter)
         self._h = ct.c_void_p()
+        self._batches = weakref.WeakSet()
         self._check(self.lib.dmrg_create(ct.byref(self._h), ct.byref(self.opts), _dp(h), _dp(g)))
         self.k = None
 
@@ -139,6 +152,8 @@ class DMRG:
         return rc
 
     def close(self):
+        for b in list(getattr(self, "_batches", ())):
+            b.close()
         if self._h:
             self.lib.dmrg_destroy(self._h)
             self._h = ct.c_void_p()
@@ -232,3 +247,48 @@ class DMRG:
         self._check(self.lib.dmrg_stats(self._h, _dp(out), 5))
         return dict(hpsi_flops=out[0], op_bytes=out[1], peak_bytes=out[2], n_terms=int(out[3]),
                     n_tasks=int(out[4]))
+
+
+class HpsiBatch:
+    """H*psi of several contexts in one grouped launch per stage (dmrg_batch_*).
+
+    The batch keeps its contexts alive; closing any of them closes the batch
+    first."""
+
+    def __init__(self, contexts, prec=FP64):
+        self.contexts = list(contexts)
+        if not self.contexts:
+            raise ValueError("HpsiBatch needs at least one context")
+        self.lib = self.contexts[0].lib
+        self.prec = prec
+        arr = (ct.c_void_p * len(self.contexts))(*[c._h.value for c in self.contexts])
+        self._h = ct.c_void_p()
+        rc = self.lib.dmrg_batch_create(arr, len(self.contexts), prec, ct.byref(self._h))
+        if rc != 0:
+            raise DMRGError(rc, self.lib.dmrg_last_error().decode())
+        for c in self.contexts:
+            c._batches.add(self)
+
+    def run(self, d_in, d_out):
+        """d_in[i], d_out[i]: device addresses of FP64 vectors of context i's length."""
+        n = len(self.contexts)
+        if len(d_in) != n or len(d_out) != n:
+            raise ValueError("one input and one output per context")
+        if not self._h:
+            raise DMRGError(-1, "batch is closed")
+        a = (ct.c_void_p * n)(*[int(p) for p in d_in])
+        b = (ct.c_void_p * n)(*[int(p) for p in d_out])
+        rc = self.lib.dmrg_batch_hpsi(self._h, a, b)
+        if rc != 0:
+            raise DMRGError(rc, self.lib.dmrg_last_error().decode())
+
+    def close(self):
+        if self._h:
+            self.lib.dmrg_batch_destroy(self._h)
+            self._h = ct.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

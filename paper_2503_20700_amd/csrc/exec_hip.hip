@@ -1066,6 +1066,10 @@ __global__ __launch_bounds__(256) void jac_apply(double* __restrict__ A, double*
   v[qu] = su * x + cu * y;
 }
 
+// Work-groups per launch of the grouped kernels: 256 threads each, and the
+// grid's work-item count must fit 32 bits.
+constexpr long long kMaxGroups = 1LL << 23;
+
 struct Prepared {
   RawJob* d_jobs = nullptr;
   RawTerm* d_terms = nullptr;
@@ -1365,7 +1369,6 @@ class HipExec : public Executor {
     std::vector<RedItem> reds;
     plan_items(jobs, terms, P->kt, P->bm, P->bn, items, reds, P->nslots);
     P->nitems = (long long)items.size();
-    if (P->nitems > 0x7fffffffLL) throw std::runtime_error("executor: too many work items in one launch");
     P->nreds = (long long)reds.size();
     if (P->nreds) pick_reduce(P->mode, dc);
     if (P->nitems) {
@@ -1401,10 +1404,15 @@ class HipExec : public Executor {
       HIP_OK(hipEventCreate(&e1));
       HIP_OK(hipEventRecord(e0, stream_));
     }
-    // one work-group per item; the hardware dispatcher balances the load
-    hipLaunchKernelGGL(k, dim3((unsigned)P->nitems), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items, part_);
+    // One work-group per item; the hardware dispatcher balances the load.  A
+    // dispatch counts its work-items in 32 bits, so a launch of more than
+    // kMaxGroups items is issued as several launches over consecutive items.
+    const long long maxg = kMaxGroups;
+    for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
+      const long long nt = std::min(maxg, P->nitems - t0);
+      hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0, part_);
+    }
     HIP_OK(hipGetLastError());
-    const long long maxg = 0x7fffffffLL;
     if (P->nreds) {
       ReduceFn r = pick_reduce(P->mode, P->dc);
       for (long long t0 = 0; t0 < P->nreds; t0 += maxg) {

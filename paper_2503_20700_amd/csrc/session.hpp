@@ -22,6 +22,7 @@ struct dmrg_ctx {
   std::unique_ptr<dmrg::HpsiPlan> plan;
   int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1, b_inp = -1;
   void* d_pidx = nullptr;  // padded psi index -> caller index (int32, -1 = padding)
+  long long plan_serial = 0;  // bumped whenever a new H*psi plan is made
   struct Prepared {
     std::vector<void*> L, R;
     bool ready = false;
@@ -86,6 +87,7 @@ struct dmrg_ctx {
   void ensure_plan() {
     if (plan) return;
     plan = C->plan_hpsi(budget());
+    ++plan_serial;
     const int64_t n = plan->lay.size;
     b_in = C->new_buf(std::max<int64_t>(n, 1));
     b_out = C->new_buf(std::max<int64_t>(n, 1));
@@ -110,9 +112,8 @@ struct dmrg_ctx {
   static int op_dt(int prec) { return prec == DMRG_FP64 ? dmrg::DT_F64 : prec == DMRG_FP32 ? dmrg::DT_F32 : dmrg::DT_BF16; }
   static int out_dt(int prec) { return prec == DMRG_FP64 ? dmrg::DT_F64 : dmrg::DT_F32; }
 
-  void prepare(int prec) {
-    Prepared& P = prep[prec];
-    if (P.ready) return;
+  // Operator families and plan buffers in the storage type of precision prec.
+  void ready_dtypes(int prec) {
     const int od = op_dt(prec), xd = op_dt(prec), outd = out_dt(prec);
     if (od != dmrg::DT_F64) {
       for (dmrg::Block* blk : {C->Lblk.get(), C->Rblk.get()}) {
@@ -126,6 +127,13 @@ struct dmrg_ctx {
       C->alloc_dtype(b_x, xd);
       C->alloc_dtype(b_out, outd);
     }
+  }
+
+  void prepare(int prec) {
+    Prepared& P = prep[prec];
+    if (P.ready) return;
+    const int od = op_dt(prec), xd = op_dt(prec), outd = out_dt(prec);
+    ready_dtypes(prec);
     bind();
     for (auto& ch : plan->chunks) {
       std::vector<dmrg::RawJob> j;

@@ -45,3 +45,20 @@ def test_create_rejects_bad_symmetry_and_nonfinite():
     with pytest.raises(DMRGError) as e:
         DMRG(h, g2, 4, 0)
     assert e.value.code == -7
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="native library not built")
+def test_batch_rejects_bad_arguments():
+    lib = ct.CDLL(LIB)
+    lib.dmrg_batch_create.argtypes = [ct.c_void_p, ct.c_int, ct.c_int, ct.POINTER(ct.c_void_p)]
+    lib.dmrg_batch_hpsi.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p]
+    lib.dmrg_batch_destroy.argtypes = [ct.c_void_p]
+    out = ct.c_void_p()
+    assert lib.dmrg_batch_create(None, 1, 0, ct.byref(out)) == -1
+    null_ctx = (ct.c_void_p * 2)(None, None)
+    assert lib.dmrg_batch_create(null_ctx, 0, 0, ct.byref(out)) == -1
+    assert lib.dmrg_batch_create(null_ctx, 2, 0, ct.byref(out)) == -1
+    assert lib.dmrg_batch_create(null_ctx, 2, 7, ct.byref(out)) == -1
+    assert not out.value
+    assert lib.dmrg_batch_hpsi(None, None, None) == -1
+    lib.dmrg_batch_destroy(None)
