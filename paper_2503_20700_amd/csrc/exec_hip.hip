@@ -518,8 +518,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
 //     sum divided by the weight of the product being multiplied, rescaled by
 //     w_prev / w_next (FP32) when a new product starts and by the last weight
 //     before write-back, so no second accumulator is needed.
+// The kernel is latency bound (short K per product, one slab in flight), so
+// the register budget is capped to keep more waves resident: 7 per SIMD for
+// 64 x 64 tiles and 4 for the larger ones, the most that compile without
+// spilling to scratch.
 template <int DC, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_bf16_padded(const RawJob* __restrict__ jobs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4096 ? 4 : 7))) void gemm_bf16_padded(const RawJob* __restrict__ jobs,
                                                         const RawTerm* __restrict__ terms,
                                                         const WorkItem* __restrict__ items, void* __restrict__ part) {
   constexpr int KT = 32, LS = KT + 8;     // LDS row stride in bf16 elements (80 bytes)
