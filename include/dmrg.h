@@ -140,6 +140,16 @@ int dmrg_davidson_step(dmrg_ctx *c, int k, double *psi_inout, double *energy, do
 int dmrg_truncate(dmrg_ctx *c, int k, const double *psi, int direction, int d_max, double eps_tr,
                   double *trunc_err, int *d_kept);
 
+/* Dynamic block state selection (Sec. "Numerical procedure": bond dimension
+ * chosen per bond at a fixed truncation error eps_tr instead of a fixed D):
+ * as dmrg_truncate, keeping the fewest multiplets whose discarded weight
+ * stays <= eps_tr of the total, clamped to [d_min, d_max] (and to the number
+ * of multiplets the cut has).  With eps_tr = 0, d_max multiplets are kept.
+ * dmrg_truncate is this call with d_min = 0.  Errors as dmrg_truncate, and
+ * ARG unless 0 <= d_min <= d_max. */
+int dmrg_truncate_dbss(dmrg_ctx *c, int k, const double *psi, int direction, int d_min, int d_max,
+                       double eps_tr, double *trunc_err, int *d_kept);
+
 /* Read back bond b's sectors ((N, 2S, dim) rows, *n sectors) and site j's
  * tensor (blocks in the canonical order of dmrg_set_mps, *n values); with a
  * NULL output only the count is returned. */

@@ -68,6 +68,7 @@ def load(path=None):
         "dmrg_heff_diag": (I, [P, I, dp]),
         "dmrg_davidson_step": (I, [P, I, dp, dp, dp, ip, ip]),
         "dmrg_truncate": (I, [P, I, dp, I, I, D, dp, ip]),
+        "dmrg_truncate_dbss": (I, [P, I, dp, I, I, I, D, dp, ip]),
         "dmrg_cut_spectrum": (I, [P, dp, ip, ip, I]),
         "dmrg_stats": (I, [P, dp, I]),
         "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
@@ -91,7 +92,7 @@ def load(path=None):
 
 def exported_symbols():
     return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_heff_diag",
-            "dmrg_davidson_step", "dmrg_truncate", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
+            "dmrg_davidson_step", "dmrg_truncate", "dmrg_truncate_dbss", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
             "dmrg_kernel_timing", "dmrg_current_block", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
             "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_last_error", "dmrg_destroy"]
 
@@ -205,11 +206,14 @@ class DMRG:
             self._check(rc)
         return dict(psi=psi, energy=e.value, resid=r.value, n_lo=nlo.value, n_fp64=nhi.value, converged=rc == 0)
 
-    def truncate(self, psi, d_max, eps_tr=0.0, direction=1):
+    def truncate(self, psi, d_max, eps_tr=0.0, direction=1, d_min=0):
+        """Truncate to d_max multiplets, or with eps_tr > 0 to the fewest whose
+        discarded weight is <= eps_tr (dynamic block state selection), kept
+        within [d_min, d_max]."""
         psi = np.ascontiguousarray(psi, dtype=np.float64)
         err, kept = ct.c_double(), ct.c_int()
-        self._check(self.lib.dmrg_truncate(self._h, self.k, _dp(psi), direction, d_max, eps_tr, ct.byref(err),
-                                           ct.byref(kept)))
+        self._check(self.lib.dmrg_truncate_dbss(self._h, self.k, _dp(psi), direction, d_min, d_max, eps_tr,
+                                                ct.byref(err), ct.byref(kept)))
         kk = ct.c_int()
         self._check(self.lib.dmrg_current_block(self._h, ct.byref(kk)))
         self.k = kk.value

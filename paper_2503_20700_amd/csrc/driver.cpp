@@ -352,9 +352,15 @@ struct CutSector {
 
 extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int d_max, double eps_tr,
                              double* trunc_err, int* d_kept) {
+  return dmrg_truncate_dbss(c, k, psi, dir, 0, d_max, eps_tr, trunc_err, d_kept);
+}
+
+extern "C" int dmrg_truncate_dbss(dmrg_ctx* c, int k, const double* psi, int dir, int d_min, int d_max,
+                                  double eps_tr, double* trunc_err, int* d_kept) {
   if (!c || !psi || !trunc_err || !d_kept) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: null argument");
   if (dir != 1 && dir != -1) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: direction must be +1 or -1");
   if (d_max < 1 || !(eps_tr >= 0.0)) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: bad d_max / eps_tr");
+  if (d_min < 0 || d_min > d_max) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: need 0 <= d_min <= d_max");
   if (!c->C->Lblk || k != c->C->k) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: no MPS loaded at this k");
   Context& C = *c->C;
   Executor* ex = c->ex.get();
@@ -464,14 +470,16 @@ extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int
       return a.sec != b.sec ? a.sec < b.sec : a.idx < b.idx;
     });
     size_t keepn = std::min<size_t>((size_t)d_max, all.size());
-    if (eps_tr > 0.0) {  // fewest multiplets whose discarded weight stays <= eps_tr
+    if (eps_tr > 0.0) {
+      // dynamic block state selection: the fewest multiplets whose discarded
+      // weight stays <= eps_tr, but at least d_min and at most d_max
       double disc = 0.0;
       size_t m = all.size();
       while (m > 1 && disc + all[m - 1].w <= eps_tr * wsum) {
         disc += all[m - 1].w;
         --m;
       }
-      keepn = std::min(keepn, m);
+      keepn = std::min(keepn, std::max(m, std::min<size_t>((size_t)d_min, all.size())));
     }
     double kept_w = 0.0;
     std::vector<std::vector<int>> kept(secs.size());

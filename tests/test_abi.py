@@ -62,3 +62,13 @@ def test_batch_rejects_bad_arguments():
     assert not out.value
     assert lib.dmrg_batch_hpsi(None, None, None) == -1
     lib.dmrg_batch_destroy(None)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="native library not built")
+def test_truncate_dbss_rejects_bad_arguments():
+    lib = ct.CDLL(LIB)
+    f = lib.dmrg_truncate_dbss
+    f.argtypes = [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_double, ct.c_void_p,
+                  ct.c_void_p]
+    err, kept = ct.c_double(), ct.c_int()
+    assert f(None, 0, None, 1, 0, 10, 0.0, ct.byref(err), ct.byref(kept)) == -1

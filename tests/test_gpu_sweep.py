@@ -10,7 +10,12 @@ the return trip needs), at CAS(8,8), S=0.
 * D = 64 truncates the middle bond: every energy lies above FCI
   (variational), the steps next to the middle bond discard weight, and the
   energies of the second pass over a block repeat those of the first
-  (the sweep has converged at this D)."""
+  (the sweep has converged at this D).
+* Dynamic block state selection (eps_tr = 1e-5 and 1e-7, D between 4 and
+  200): every step discards at most eps_tr unless D_min binds, energies are
+  variational, the tighter eps_tr keeps more multiplets and ends closer to
+  FCI (within 1e-5 Eh), and the looser one keeps fewer multiplets than the
+  complete middle bond holds."""
 import numpy as np
 import pytest
 
@@ -21,7 +26,7 @@ from synth.mps import random_mps
 pytestmark = pytest.mark.gpu
 
 
-def _sweep(prec, d):
+def _sweep(prec, d, eps_tr=0.0, d_min=0):
     from paper_2503_20700_amd.binding import DMRG
     n, ne, ts = 8, 8, 0
     h, g, _ = small_cas(n, 0)
@@ -36,8 +41,8 @@ def _sweep(prec, d):
         _, nel = dm.psi_layout()
         r = dm.davidson(np.zeros(nel))
         assert r["converged"], r
-        err, kept = dm.truncate(r["psi"], d, 0.0, direction)
-        steps.append((k, direction, r["energy"], err))
+        err, kept = dm.truncate(r["psi"], d, eps_tr, direction, d_min=d_min)
+        steps.append((k, direction, r["energy"], err, kept))
         assert dm.k >= 0
     dm.close()
     return e_fci, steps
@@ -46,8 +51,9 @@ def _sweep(prec, d):
 @pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "bf16+jd"])
 def test_sweep_complete_bonds_is_exact(prec):
     e_fci, steps = _sweep(prec, 200)
-    print(f"[sweep D=200] prec={prec} worst |E-FCI|={max(abs(e - e_fci) for _, _, e, _ in steps):.2e}", flush=True)
-    for k, _, e, err in steps:
+    print(f"[sweep D=200] prec={prec} worst |E-FCI|={max(abs(e - e_fci) for _, _, e, _, _ in steps):.2e}",
+          flush=True)
+    for k, _, e, err, _ in steps:
         assert abs(e - e_fci) < 1e-8, (k, e, e_fci)
         assert err < 1e-12
 
@@ -55,14 +61,32 @@ def test_sweep_complete_bonds_is_exact(prec):
 @pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "bf16+jd"])
 def test_sweep_truncated_is_variational_and_converged(prec):
     e_fci, steps = _sweep(prec, 64)
-    print(f"[sweep D=64] prec={prec} E-FCI=" + " ".join(f"{e - e_fci:.2e}" for _, _, e, _ in steps), flush=True)
-    assert min(e for _, _, e, _ in steps) >= e_fci - 1e-8
-    assert max(err for _, _, _, err in steps) > 1e-4  # the middle bond is truncated
+    print(f"[sweep D=64] prec={prec} E-FCI=" + " ".join(f"{e - e_fci:.2e}" for _, _, e, _, _ in steps), flush=True)
+    assert min(e for _, _, e, _, _ in steps) >= e_fci - 1e-8
+    assert max(err for _, _, _, err, _ in steps) > 1e-4  # the middle bond is truncated
     # blocks visited twice in the same direction give the same energy
     first = {}
-    for k, direction, e, _ in steps:
+    for k, direction, e, _, _ in steps:
         key = (k, direction)
         if key in first:
             assert abs(e - first[key]) < 1e-6, (key, e, first[key])
         else:
             first[key] = e
+
+
+@pytest.mark.parametrize("prec", [0, 2], ids=["fp64", "bf16+jd"])
+def test_sweep_dbss(prec):
+    d_min, res = 4, {}
+    for eps in (1e-5, 1e-7):
+        e_fci, steps = _sweep(prec, 200, eps, d_min)
+        res[eps] = steps
+        print(f"[sweep DBSS] prec={prec} eps={eps:.0e} kept=" + " ".join(str(m) for *_, m in steps)
+              + f" final E-FCI={steps[-1][2] - e_fci:.2e}", flush=True)
+        for k, _, e, err, kept in steps:
+            assert e >= e_fci - 1e-8, (k, e, e_fci)
+            assert err <= eps or kept <= d_min, (k, err, kept)  # the cut may hold fewer than d_min
+    loose, tight = res[1e-5], res[1e-7]
+    assert max(m for *_, m in loose) < 126  # the middle bond is not kept complete
+    assert abs(tight[-1][2] - e_fci) < 1e-5
+    assert abs(tight[-1][2] - e_fci) < abs(loose[-1][2] - e_fci)
+    assert sum(m for *_, m in tight) > sum(m for *_, m in loose)

@@ -146,3 +146,26 @@ def test_cut_spectrum_at_cas32_d1024_matches_numpy():
     print(f"[cut spectrum] sectors={len(by_a)} max dim={max(len(ms[0]) for ms in by_a.values())} n={len(w)}", flush=True)
     assert abs(w.sum() - 1.0) < 1e-12
     assert np.abs(w - ref[:len(w)]).max() < 1e-13
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_dbss_selection_matches_oracle(direction):
+    # Dynamic block state selection: the kept count and the discarded weight
+    # equal the oracle's rule applied to the multiplet weights it derives from
+    # the Fock-space Schmidt values of the same (singlet) wavefunction.
+    case = (8, 8, 0, 64, 3, 0)
+    h, g, mps, psi, lay, dm = _ctx(case)
+    w, _ = otr.multiplet_weights(otr.schmidt_values(mps, lay, psi))
+    tail = np.concatenate([np.cumsum(w[::-1])[::-1], [0.0]]) / w.sum()
+    eps20 = tail[20] * 1.000001  # just admits discarding everything past 20
+    eps31 = tail[31] * 0.999999  # just too small to stop at 31
+    for eps, d_min, d_max in [(eps20, 0, 10 ** 6), (eps20, 25, 10 ** 6), (eps20, 0, 15), (eps31, 0, 10 ** 6),
+                              (0.5, 3, 100), (0.0, 0, 17)]:
+        print(f"[dbss] dir={direction} eps={eps:.3e} d_min={d_min} d_max={d_max}", flush=True)
+        h, g, mps, psi, lay, dm = _ctx(case)
+        err, kept = dm.truncate(psi, d_max, eps, direction, d_min=d_min)
+        want = otr.dbss_keep(w, eps, d_min, d_max)
+        assert kept == want, (kept, want)
+        assert abs(err - tail[want]) < 1e-12
+        if eps > 0 and d_min < kept < d_max:  # neither clamp active
+            assert err <= eps

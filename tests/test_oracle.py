@@ -171,3 +171,40 @@ def test_leading_csf_middle_cut_has_six_equal_schmidt_values():
     s = np.linalg.svd(mat.T, compute_uv=False)
     nz = s[s > 1e-12]
     assert len(nz) == 6 and np.allclose(nz, 1 / np.sqrt(6))
+    # the same run of six equal values is one S=5/2 multiplet of weight 1
+    from oracle import truncate as otr2
+    w, s2 = otr2.multiplet_weights(s)
+    assert s2.tolist() == [5] and abs(w[0] - 1.0) < 1e-12
+
+
+def test_multiplet_grouping_recovers_a_constructed_spectrum():
+    # multiplets (weight, 2S) expanded to 2S+1 Schmidt values sqrt(w/(2S+1))
+    # each, shuffled, with a null space of zeros and rounding-level noise
+    from oracle import truncate as otr
+    mult = [(0.41, 0), (0.22, 2), (0.17, 1), (0.09, 4), (0.06, 0), (0.03, 3), (0.02, 2)]
+    vals = []
+    for wt, ts in mult:
+        vals += [np.sqrt(wt / (ts + 1))] * (ts + 1)
+    vals = np.array(vals + [0.0] * 7 + [1e-17] * 3)
+    np.random.default_rng(0).shuffle(vals)
+    w, s2 = otr.multiplet_weights(vals)
+    assert np.allclose(w, [m[0] for m in mult], rtol=0, atol=1e-15)
+    assert s2.tolist() == [m[1] for m in mult]
+
+
+def test_dbss_keep_worked_example():
+    # weights 0.6, 0.25, 0.1, 0.04, 0.01 (total 1): keeping 3 discards 0.05,
+    # keeping 4 discards 0.01, keeping 2 discards 0.15
+    from oracle import truncate as otr
+    w = [0.04, 0.6, 0.01, 0.25, 0.1]  # order must not matter
+    assert otr.dbss_keep(w, 0.0501, 0, 100) == 3
+    assert otr.dbss_keep(w, 0.0499, 0, 100) == 4
+    assert otr.dbss_keep(w, 0.0099, 0, 100) == 5
+    assert otr.dbss_keep(w, 0.1501, 0, 100) == 2
+    assert otr.dbss_keep(w, 0.1499, 0, 100) == 3
+    assert otr.dbss_keep(w, 0.9, 0, 100) == 1     # never below one multiplet
+    assert otr.dbss_keep(w, 0.0501, 4, 100) == 4  # d_min raises
+    assert otr.dbss_keep(w, 0.0501, 0, 2) == 2    # d_max caps
+    assert otr.dbss_keep(w, 0.0501, 9, 9) == 5    # capped by the count
+    assert otr.dbss_keep(w, 0.0, 0, 4) == 4       # eps 0: fixed D
+    assert otr.dbss_keep(w, 0.0, 0, 100) == 5
