@@ -804,6 +804,182 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4
       }
 }
 
+// BF16 kernel for padded launches dominated by small blocks (many output
+// matrices of a few rows or columns, where a 64 x 64 tile is mostly empty):
+// each wave owns one 32 x 32 output tile (2 x 2 blocks of
+// v_mfma_f32_16x16x32_bf16) and the four waves of a work-group serve four
+// independent work items.  Operands go from memory straight into the MFMA
+// registers -- one 16-byte vector per lane and block where the operand is
+// contiguous along k, eight 2-byte loads where it is contiguous along m (n)
+// -- so there is no LDS and no barrier; the next slab is loaded before the
+// current one is multiplied.  Product weights use the scaled accumulator
+// frame of gemm_bf16_padded.  Same work items, split-K slots and reduction as
+// the other kernels, with bm = bn = 32.  The register budget is capped at 6
+// waves per SIMD, the most that compiles without scratch.
+template <int DC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void gemm_bf16_wave(const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms,
+                                                      const WorkItem* __restrict__ items, void* __restrict__ part,
+                                                      long long nitems) {
+  constexpr int T = 32, KT = 32;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long long it = (long long)blockIdx.x * 4 + wv;
+  if (it >= nitems) return;  // whole wave; the kernel has no barrier
+  const WorkItem W = items[it];
+  const RawJob J = jobs[W.job];
+  const int m0 = W.ti * T, n0 = W.tj * T;
+  const int lr = lane & 15, lg = lane >> 4;
+  f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  // identity products, in the unscaled frame
+  if (W.has_ident)
+    for (int t = W.tbeg; t < W.tend; ++t) {
+      const int fl = terms[t].flags;
+      if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+      const RawTerm Ti = terms[t];
+      const bool ia = fl & TF_IDENT_A;
+      const u16* P = (const u16*)(ia ? Ti.B : Ti.A);
+      const long long ld = ia ? Ti.ldb : Ti.lda;
+      const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = m0 + a * 16 + 4 * lg + v, col = n0 + b * 16 + lr;
+            if (row < J.m && col < J.n)
+              acc[a][b][v] += (float)Ti.alpha * bf2f(P[tr ? (long long)col * ld + row : (long long)row * ld + col]);
+          }
+    }
+  // slab k0 of product Tm into this lane's operand registers: k = k0 + 8 lg + j
+  auto fetch = [&](const RawTerm& Tm, int k0, uint4 (&ra)[2], uint4 (&rb)[2]) {
+    const int kb = k0 + 8 * lg, nk = Tm.k - kb;
+    const u16* A = (const u16*)Tm.A;
+    const u16* B = (const u16*)Tm.B;
+    const bool aK = !(Tm.flags & TF_TRANS_A);  // A stored m x k
+    const bool bK = (Tm.flags & TF_TRANS_B);   // B stored n x k
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int r = m0 + a * 16 + lr;
+      ra[a] = make_uint4(0, 0, 0, 0);
+      if (r < J.m && nk > 0) {
+        if (aK) {
+          ra[a] = *(const uint4*)(A + (long long)r * Tm.lda + kb);
+          if (nk < 8) ra[a] = keep_first<2>(ra[a], nk);
+        } else {
+          unsigned w[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const unsigned lo = (2 * q < nk) ? A[(long long)(kb + 2 * q) * Tm.lda + r] : 0u;
+            const unsigned hi = (2 * q + 1 < nk) ? A[(long long)(kb + 2 * q + 1) * Tm.lda + r] : 0u;
+            w[q] = lo | (hi << 16);
+          }
+          ra[a] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int c = n0 + b * 16 + lr;
+      rb[b] = make_uint4(0, 0, 0, 0);
+      if (c < J.n && nk > 0) {
+        if (bK) {
+          rb[b] = *(const uint4*)(B + (long long)c * Tm.ldb + kb);
+          if (nk < 8) rb[b] = keep_first<2>(rb[b], nk);
+        } else {
+          unsigned w[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const unsigned lo = (2 * q < nk) ? B[(long long)(kb + 2 * q) * Tm.ldb + c] : 0u;
+            const unsigned hi = (2 * q + 1 < nk) ? B[(long long)(kb + 2 * q + 1) * Tm.ldb + c] : 0u;
+            w[q] = lo | (hi << 16);
+          }
+          rb[b] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      }
+    }
+  };
+  auto next_dense = [&](int t) {
+    while (t < W.tend && (terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) ++t;
+    return t;
+  };
+  uint4 ra[2], rb[2], na[2], nb[2];
+  int t = W.dense0, k0 = 0;
+  float scale = 1.f;  // acc holds the partial sum divided by scale
+  RawTerm Tc;
+  if (t < W.tend) {
+    Tc = terms[t];
+    fetch(Tc, 0, ra, rb);
+  }
+  while (t < W.tend) {
+    int t2 = t, k2 = k0 + KT;
+    RawTerm Tn = Tc;
+    if (k2 >= Tc.k) {
+      t2 = next_dense(t + 1);
+      k2 = 0;
+      if (t2 < W.tend) Tn = terms[t2];
+    }
+    if (t2 < W.tend) fetch(Tn, k2, na, nb);
+    const float alpha = (float)Tc.alpha;
+    if (k0 == 0 && alpha != scale) {
+      // product t starts: move the accumulator into its frame
+      const float r = scale / alpha;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] *= r;
+      scale = alpha;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ra[a]),
+                                                            __builtin_bit_cast(bf8, rb[b]), acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      ra[a] = na[a];
+      rb[a] = nb[a];
+    }
+    t = t2;
+    k0 = k2;
+    Tc = Tn;
+  }
+  if (scale != 1.f) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] *= scale;
+  }
+  if (W.slot >= 0) {
+    float* P = (float*)part + (long long)W.slot * (T * T);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[(a * 16 + 4 * lg + v) * T + b * 16 + lr] = acc[a][b][v];
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + a * 16 + 4 * lg + v, col = n0 + b * 16 + lr;
+        if (row < J.m && col < J.n) {
+          const long long o = (long long)row * J.ldc + col;
+          if (J.accumulate) stv<DC>(J.C, o, ldv<DC>(J.C, o) + (double)acc[a][b][v]);
+          else stv<DC>(J.C, o, acc[a][b][v]);
+        }
+      }
+}
+
 // Sum of the partial tiles (bm x bn values each) of split items, in slot
 // order, into C.
 template <int MODE, int DC>
@@ -1082,10 +1258,12 @@ struct Prepared {
   long long nitems = 0, nreds = 0, nslots = 0;
   int mode = DT_F64, da = DT_F64, db = DT_F64, dc = DT_F64, kt = 16;
   bool padded = false;  // BF16 launch served by gemm_bf16_padded
+  bool wave = false;    // ... or by gemm_bf16_wave (32 x 32 tile per wave)
   int bm = TM, bn = TN;  // output tile of the launch
 };
 
 using KernelFn = void (*)(const RawJob*, const RawTerm*, const WorkItem*, void*);
+using WaveFn = void (*)(const RawJob*, const RawTerm*, const WorkItem*, void*, long long);
 using ReduceFn = void (*)(const RawJob*, const RedItem*, const void*, int, int);
 
 KernelFn pick(int mode, int da, int db, int dc, int kt) {
@@ -1137,6 +1315,29 @@ void choose_tile(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& te
     if (work[c] <= 1.1 * wmin && (work[best] > 1.1 * wmin || tiles[c] < tiles[best])) best = c;
   bm = cand[best][0];
   bn = cand[best][1];
+}
+
+// Whether a padded BF16 launch goes to gemm_bf16_wave: when its padded MFMA
+// work with 32 x 32 tiles (one wave each) is below 0.6 of that with 64 x 64
+// tiles, i.e. when most 64 x 64 tiles would be largely empty.
+// DMRG_WAVE=0 / 1 forces the choice.
+bool choose_wave(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms) {
+  if (const char* e = std::getenv("DMRG_WAVE")) return std::atoi(e) != 0;
+  double w32 = 0.0, w64 = 0.0;
+  for (const RawJob& J : jobs) {
+    double kpad = 0.0;
+    for (int64_t t = J.tbeg; t < J.tend; ++t)
+      if (!(terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) kpad += (double)((terms[t].k + 31) / 32 * 32);
+    w32 += (double)((J.m + 31) / 32) * (double)((J.n + 31) / 32) * 1024.0 * kpad;
+    w64 += (double)((J.m + 63) / 64) * (double)((J.n + 63) / 64) * 4096.0 * kpad;
+  }
+  return w32 < 0.6 * w64;
+}
+
+WaveFn pick_wave(int dc) {
+  if (dc == DT_BF16) return gemm_bf16_wave<DT_BF16>;
+  if (dc == DT_F32) return gemm_bf16_wave<DT_F32>;
+  throw std::runtime_error("executor: unsupported wave-kernel output type");
 }
 
 // K slab of a BF16 launch: 64 when that pads the products' K by at most 1/8
@@ -1366,7 +1567,11 @@ class HipExec : public Executor {
       P->padded = ok && !std::getenv("DMRG_NO_PADDED_KERNEL");
     }
     P->kt = P->padded ? 32 : (P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16);
-    if (P->padded) choose_tile(jobs, terms, P->bm, P->bn);
+    if (P->padded) {
+      P->wave = choose_wave(jobs, terms);
+      if (P->wave) P->bm = P->bn = 32;
+      else choose_tile(jobs, terms, P->bm, P->bn);
+    }
     pick(P->mode, da, db, dc, P->kt);  // validate
     if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
     std::vector<WorkItem> items;
@@ -1401,7 +1606,6 @@ class HipExec : public Executor {
   void run(void* h) override {
     auto* P = (Prepared*)h;
     if (!P->nitems) return;
-    KernelFn k = P->padded ? pick_padded(P->dc, P->bm, P->bn) : pick(P->mode, P->da, P->db, P->dc, P->kt);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timing_) {
       HIP_OK(hipEventCreate(&e0));
@@ -1412,9 +1616,20 @@ class HipExec : public Executor {
     // dispatch counts its work-items in 32 bits, so a launch of more than
     // kMaxGroups items is issued as several launches over consecutive items.
     const long long maxg = kMaxGroups;
-    for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
-      const long long nt = std::min(maxg, P->nitems - t0);
-      hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0, part_);
+    if (P->wave) {
+      // four items per work-group, one per wave
+      WaveFn k = pick_wave(P->dc);
+      for (long long t0 = 0; t0 < P->nitems; t0 += 4 * maxg) {
+        const long long nt = std::min(4 * maxg, P->nitems - t0);
+        hipLaunchKernelGGL(k, dim3((unsigned)((nt + 3) / 4)), dim3(256), 0, stream_, P->d_jobs, P->d_terms,
+                           P->d_items + t0, part_, nt);
+      }
+    } else {
+      KernelFn k = P->padded ? pick_padded(P->dc, P->bm, P->bn) : pick(P->mode, P->da, P->db, P->dc, P->kt);
+      for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
+        const long long nt = std::min(maxg, P->nitems - t0);
+        hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0, part_);
+      }
     }
     HIP_OK(hipGetLastError());
     if (P->nreds) {

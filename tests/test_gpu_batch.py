@@ -141,3 +141,12 @@ def test_batch48_full_size_self_consistent():
                 assert herm < 1e-12, herm
     for dm in dms:
         dm.close()
+
+
+@pytest.mark.parametrize("wave", ["0", "1"], ids=["lean", "wave"])
+def test_batch_bf16_each_kernel(instances, wave, monkeypatch):
+    # the merged BF16 launches on either padded kernel, against the oracle
+    monkeypatch.setenv("DMRG_WAVE", wave)
+    first, _ = _run_batch(instances, 2)
+    for x, y in zip(instances, first):
+        assert np.abs(y - x["ref"]).max() < 2.0 ** -8 * 8 * np.abs(x["ref"]).max()

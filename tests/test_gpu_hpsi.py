@@ -71,7 +71,7 @@ def test_heff_diag_matches_oracle_dense():
 
 @pytest.mark.parametrize("prec,bound,kt", [(1, 2.0 ** -24 * 64, ""), (2, 2.0 ** -8 * 8, "32"),
                                            (2, 2.0 ** -8 * 8, "64"), (2, 2.0 ** -8 * 8, "")])
-@pytest.mark.parametrize("kernel", ["lean", "generic", "64x64", "64x128", "128x64"])
+@pytest.mark.parametrize("kernel", ["lean", "generic", "64x64", "64x128", "128x64", "wave"])
 def test_hpsi_low_precision_error_bound(prec, bound, kt, kernel, monkeypatch):
     # BF16 H*psi launches run on the lean padded-operand kernel unless it is
     # switched off; the generic kernel then runs with K slabs of 32 or 64.
@@ -79,8 +79,12 @@ def test_hpsi_low_precision_error_bound(prec, bound, kt, kernel, monkeypatch):
         monkeypatch.setenv("DMRG_BF16_KT", kt)  # else chosen per launch
     if kernel == "generic":
         monkeypatch.setenv("DMRG_NO_PADDED_KERNEL", "1")
-    elif kernel != "lean":
-        monkeypatch.setenv("DMRG_TILE", kernel)
+    elif kernel == "wave":
+        monkeypatch.setenv("DMRG_WAVE", "1")  # 32x32 tile per wave, identity products included
+    else:
+        monkeypatch.setenv("DMRG_WAVE", "0")
+        if kernel != "lean":
+            monkeypatch.setenv("DMRG_TILE", kernel)
     case = (10, 10, 0, 40, 4, 6)
     h, g, mps, psi, lay, dm = _setup(*case)
     y64, _ = dm.hpsi(psi, 0)

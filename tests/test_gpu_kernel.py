@@ -84,10 +84,14 @@ def test_gemm_bf16_lean_and_generic_kernels_agree(m, n, k, monkeypatch):
     rng = np.random.default_rng(11)
     a = rng.normal(size=(m, k))
     b = rng.normal(size=(k, n))
+    monkeypatch.setenv("DMRG_WAVE", "0")
     lean = gemm_selftest(a, b, alpha=-1.25, prec=2, pad_a=True, pad_b=True)
+    monkeypatch.setenv("DMRG_WAVE", "1")
+    wave = gemm_selftest(a, b, alpha=-1.25, prec=2, pad_a=True, pad_b=True)
     monkeypatch.setenv("DMRG_NO_PADDED_KERNEL", "1")
     generic = gemm_selftest(a, b, alpha=-1.25, prec=2, pad_a=True, pad_b=True)
     assert np.abs(lean - generic).max() <= 1e-5 * np.abs(generic).max()
+    assert np.abs(wave - generic).max() <= 1e-5 * np.abs(generic).max()
 
 
 @pytest.mark.parametrize("tile", ["64x64", "64x128", "128x64"])
@@ -96,6 +100,7 @@ def test_gemm_bf16_lean_and_generic_kernels_agree(m, n, k, monkeypatch):
 def test_gemm_bf16_lean_tile_shapes(tile, m, n, k, ta, tb, monkeypatch):
     # Every output tile shape of the lean BF16 kernel on NaN-padded operands.
     monkeypatch.setenv("DMRG_TILE", tile)
+    monkeypatch.setenv("DMRG_WAVE", "0")
     from paper_2503_20700_amd.binding import gemm_selftest
     rng = np.random.default_rng(m + 3 * n + 7 * k)
     a = rng.normal(size=(m, k))
@@ -105,5 +110,26 @@ def test_gemm_bf16_lean_tile_shapes(tile, m, n, k, ta, tb, monkeypatch):
                         alpha=0.5, beta=1.0, prec=2, pad_a=True, pad_b=True)
     ref = c0 + 0.5 * (a @ b)
     bound = (2 * 2.0 ** -8 + k * 2.0 ** -24) * 0.5 * (np.abs(a) @ np.abs(b)) + 2.0 ** -24 * np.abs(ref)
+    assert np.all(np.isfinite(got))
+    assert np.all(np.abs(got - ref) <= 4 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (5, 3, 40), (32, 32, 32), (33, 31, 65), (65, 63, 17), (7, 200, 129),
+                                   (200, 9, 5)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_gemm_bf16_wave_kernel(m, n, k, ta, tb, beta, monkeypatch):
+    # The one-wave-per-32x32-tile BF16 kernel on NaN-padded operands: vector
+    # loads along k, element loads along m / n, ragged edges, accumulation.
+    monkeypatch.setenv("DMRG_WAVE", "1")
+    from paper_2503_20700_amd.binding import gemm_selftest
+    rng = np.random.default_rng(m + 5 * n + 11 * k)
+    a = rng.normal(size=(m, k))
+    b = rng.normal(size=(k, n))
+    c0 = rng.normal(size=(m, n))
+    got = gemm_selftest(a.T.copy() if ta else a, b.T.copy() if tb else b, C=c0, trans_a=bool(ta), trans_b=bool(tb),
+                        alpha=-0.625, beta=beta, prec=2, pad_a=True, pad_b=True)
+    ref = beta * c0 - 0.625 * (a @ b)
+    bound = (2 * 2.0 ** -8 + k * 2.0 ** -24) * 0.625 * (np.abs(a) @ np.abs(b)) + 2.0 ** -24 * np.abs(ref)
     assert np.all(np.isfinite(got))
     assert np.all(np.abs(got - ref) <= 4 * bound + 1e-30)
