@@ -980,6 +980,140 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void g
       }
 }
 
+// FP64 counterpart of gemm_bf16_wave for launches of mostly small blocks:
+// one wave per 32 x 32 output tile (2 x 2 blocks of v_mfma_f64_16x16x4f64),
+// four independent work items per work-group, K slabs of 16.  Each lane
+// loads its operand elements (row or column lr, k = k0 + 4 s + lg) directly;
+// 8-byte loads need no padding or alignment, so any FP64 launch qualifies.
+// The product weight multiplies A as it is loaded, as in gemm_kernel.  The
+// register cap keeps 4 waves per SIMD (127 VGPRs, no scratch).
+template <int DUMMY>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_f64_wave(const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms,
+                                                     const WorkItem* __restrict__ items, void* __restrict__ part,
+                                                     long long nitems) {
+  constexpr int T = 32, KT = 16;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const long long it = (long long)blockIdx.x * 4 + wv;
+  if (it >= nitems) return;  // whole wave; the kernel has no barrier
+  const WorkItem W = items[it];
+  const RawJob J = jobs[W.job];
+  const int m0 = W.ti * T, n0 = W.tj * T;
+  const int lr = lane & 15, lg = lane >> 4;
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  if (W.has_ident)
+    for (int t = W.tbeg; t < W.tend; ++t) {
+      const int fl = terms[t].flags;
+      if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+      const RawTerm Ti = terms[t];
+      const bool ia = fl & TF_IDENT_A;
+      const double* P = (const double*)(ia ? Ti.B : Ti.A);
+      const long long ld = ia ? Ti.ldb : Ti.lda;
+      const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = m0 + a * 16 + acc_row<DT_F64>(lg, v), col = n0 + b * 16 + lr;
+            if (row < J.m && col < J.n)
+              acc[a][b][v] += Ti.alpha * P[tr ? (long long)col * ld + row : (long long)row * ld + col];
+          }
+    }
+  // slab k0 of product Tm: ra[a][s] = alpha A(m0 + 16 a + lr, k0 + 4 s + lg),
+  // rb[b][s] = B(k0 + 4 s + lg, n0 + 16 b + lr), zero outside the matrices
+  auto fetch = [&](const RawTerm& Tm, int k0, double (&ra)[2][4], double (&rb)[2][4]) {
+    const double* A = (const double*)Tm.A;
+    const double* B = (const double*)Tm.B;
+    const bool ta = Tm.flags & TF_TRANS_A, tb = Tm.flags & TF_TRANS_B;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int r = m0 + a * 16 + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 4 * q + lg;
+        ra[a][q] = (r < J.m && k < Tm.k) ? Tm.alpha * A[ta ? (long long)k * Tm.lda + r : (long long)r * Tm.lda + k] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int c = n0 + b * 16 + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + 4 * q + lg;
+        rb[b][q] = (c < J.n && k < Tm.k) ? B[tb ? (long long)c * Tm.ldb + k : (long long)k * Tm.ldb + c] : 0.0;
+      }
+    }
+  };
+  auto next_dense = [&](int t) {
+    while (t < W.tend && (terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) ++t;
+    return t;
+  };
+  double ra[2][4], rb[2][4], na[2][4], nb[2][4];
+  int t = W.dense0, k0 = 0;
+  RawTerm Tc;
+  if (t < W.tend) {
+    Tc = terms[t];
+    fetch(Tc, 0, ra, rb);
+  }
+  while (t < W.tend) {
+    int t2 = t, k2 = k0 + KT;
+    RawTerm Tn = Tc;
+    if (k2 >= Tc.k) {
+      t2 = next_dense(t + 1);
+      k2 = 0;
+      if (t2 < W.tend) Tn = terms[t2];
+    }
+    if (t2 < W.tend) fetch(Tn, k2, na, nb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[a][q], rb[b][q], acc[a][b], 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ra[a][q] = na[a][q];
+        rb[a][q] = nb[a][q];
+      }
+    t = t2;
+    k0 = k2;
+    Tc = Tn;
+  }
+  if (W.slot >= 0) {
+    double* P = (double*)part + (long long)W.slot * (T * T);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[(a * 16 + acc_row<DT_F64>(lg, v)) * T + b * 16 + lr] = acc[a][b][v];
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + a * 16 + acc_row<DT_F64>(lg, v), col = n0 + b * 16 + lr;
+        if (row < J.m && col < J.n) {
+          const long long o = (long long)row * J.ldc + col;
+          double* C = (double*)J.C;
+          if (J.accumulate) C[o] += acc[a][b][v];
+          else C[o] = acc[a][b][v];
+        }
+      }
+}
+
 // Sum of the partial tiles (bm x bn values each) of split items, in slot
 // order, into C.
 template <int MODE, int DC>
@@ -1317,24 +1451,27 @@ void choose_tile(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& te
   bn = cand[best][1];
 }
 
-// Whether a padded BF16 launch goes to gemm_bf16_wave: when its padded MFMA
-// work with 32 x 32 tiles (one wave each) is below 0.6 of that with 64 x 64
-// tiles, i.e. when most 64 x 64 tiles would be largely empty.
+// Whether a launch goes to a wave kernel (gemm_bf16_wave for padded BF16,
+// gemm_f64_wave for FP64): when its padded MFMA work with 32 x 32 tiles (one
+// wave each) is below 0.6 of that with 64 x 64 tiles, i.e. when most 64 x 64
+// tiles would be largely empty.  kt: the K slab the padding is counted in.
 // DMRG_WAVE=0 / 1 forces the choice.
-bool choose_wave(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms) {
+bool choose_wave(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int kt) {
   if (const char* e = std::getenv("DMRG_WAVE")) return std::atoi(e) != 0;
   double w32 = 0.0, w64 = 0.0;
   for (const RawJob& J : jobs) {
     double kpad = 0.0;
     for (int64_t t = J.tbeg; t < J.tend; ++t)
-      if (!(terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) kpad += (double)((terms[t].k + 31) / 32 * 32);
+      if (!(terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) kpad += (double)((terms[t].k + kt - 1) / kt * kt);
     w32 += (double)((J.m + 31) / 32) * (double)((J.n + 31) / 32) * 1024.0 * kpad;
     w64 += (double)((J.m + 63) / 64) * (double)((J.n + 63) / 64) * 4096.0 * kpad;
   }
   return w32 < 0.6 * w64;
 }
 
-WaveFn pick_wave(int dc) {
+WaveFn pick_wave(int mode, int dc) {
+  if (mode == DT_F64 && dc == DT_F64) return gemm_f64_wave<0>;
+  if (mode != DT_BF16) throw std::runtime_error("executor: unsupported wave-kernel mode");
   if (dc == DT_BF16) return gemm_bf16_wave<DT_BF16>;
   if (dc == DT_F32) return gemm_bf16_wave<DT_F32>;
   throw std::runtime_error("executor: unsupported wave-kernel output type");
@@ -1568,9 +1705,12 @@ class HipExec : public Executor {
     }
     P->kt = P->padded ? 32 : (P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16);
     if (P->padded) {
-      P->wave = choose_wave(jobs, terms);
+      P->wave = choose_wave(jobs, terms, 32);
       if (P->wave) P->bm = P->bn = 32;
       else choose_tile(jobs, terms, P->bm, P->bn);
+    } else if (P->mode == DT_F64 && dc == DT_F64 && !std::getenv("DMRG_NO_F64_WAVE")) {
+      P->wave = choose_wave(jobs, terms, 16);
+      if (P->wave) P->bm = P->bn = 32;
     }
     pick(P->mode, da, db, dc, P->kt);  // validate
     if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
@@ -1618,7 +1758,7 @@ class HipExec : public Executor {
     const long long maxg = kMaxGroups;
     if (P->wave) {
       // four items per work-group, one per wave
-      WaveFn k = pick_wave(P->dc);
+      WaveFn k = pick_wave(P->mode, P->dc);
       for (long long t0 = 0; t0 < P->nitems; t0 += 4 * maxg) {
         const long long nt = std::min(4 * maxg, P->nitems - t0);
         hipLaunchKernelGGL(k, dim3((unsigned)((nt + 3) / 4)), dim3(256), 0, stream_, P->d_jobs, P->d_terms,

@@ -107,11 +107,14 @@ def test_hermiticity_fp64():
 
 
 @pytest.mark.parametrize("steps", ["1", "3"])
-def test_hpsi_split_k_matches_oracle(steps, monkeypatch):
+@pytest.mark.parametrize("wave", ["0", "1"], ids=["tile64", "wave32"])
+def test_hpsi_split_k_matches_oracle(steps, wave, monkeypatch):
     # Force the executor to cut every output tile's product list into pieces
     # of at most `steps` K steps, so that nearly every tile is summed from
-    # partial tiles by the reduction launch (block builds included).
+    # partial tiles by the reduction launch (block builds included), with
+    # 64x64 tiles or with the 32x32 one-wave tiles.
     monkeypatch.setenv("DMRG_SPLIT_STEPS", steps)
+    monkeypatch.setenv("DMRG_WAVE", wave)
     case = (10, 10, 0, 40, 4, 6)
     print(f"[hpsi split-K] steps={steps} case={case}", flush=True)
     h, g, mps, psi, lay, dm = _setup(*case)
@@ -122,3 +125,17 @@ def test_hpsi_split_k_matches_oracle(steps, monkeypatch):
     assert np.array_equal(y, y2)
     ylo, _ = dm.hpsi(psi, 2)
     assert np.abs(ylo - ref).max() < 2.0 ** -8 * 8 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("wave", ["0", "1"], ids=["tile64", "wave32"])
+@pytest.mark.parametrize("case", [CASES[2], CASES[6], CASES[7]], ids=["n7S1", "n10D40", "n11D500"])
+def test_hpsi_fp64_each_kernel(case, wave, monkeypatch):
+    # every FP64 launch (block builds included) on one kernel or the other
+    monkeypatch.setenv("DMRG_WAVE", wave)
+    print(f"[hpsi fp64 kernel] wave={wave} case={case}", flush=True)
+    h, g, mps, psi, lay, dm = _setup(*case)
+    y, _ = dm.hpsi(psi)
+    ref = heff.hpsi(h, g, mps, lay, psi)
+    assert np.abs(y - ref).max() < 1e-10 * np.abs(ref).max()
+    y2, _ = dm.hpsi(psi)
+    assert np.array_equal(y, y2)

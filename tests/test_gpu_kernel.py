@@ -11,7 +11,11 @@ SHAPES = [(1, 1, 1), (16, 16, 4), (64, 64, 16), (65, 63, 17), (130, 70, 33), (7,
 
 @pytest.mark.parametrize("m,n,k", SHAPES)
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
-def test_gemm_fp64(m, n, k, ta, tb):
+@pytest.mark.parametrize("wave", ["", "0", "1"], ids=["auto", "tile64", "wave32"])
+def test_gemm_fp64(m, n, k, ta, tb, wave, monkeypatch):
+    # FP64 on the 64x64-tile kernel and on the one-wave-per-32x32-tile kernel
+    if wave:
+        monkeypatch.setenv("DMRG_WAVE", wave)
     from paper_2503_20700_amd.binding import gemm_selftest
     rng = np.random.default_rng(m * 1000 + n * 10 + k)
     a = rng.normal(size=(m, k))
@@ -24,7 +28,9 @@ def test_gemm_fp64(m, n, k, ta, tb):
 
 
 @pytest.mark.parametrize("m,n", [(1, 1), (65, 63), (130, 7)])
-def test_gemm_identity_operands(m, n):
+@pytest.mark.parametrize("wave", ["0", "1"], ids=["tile64", "wave32"])
+def test_gemm_identity_operands(m, n, wave, monkeypatch):
+    monkeypatch.setenv("DMRG_WAVE", wave)
     from paper_2503_20700_amd.binding import gemm_selftest
     rng = np.random.default_rng(3)
     b = rng.normal(size=(m, n))
