@@ -1507,11 +1507,14 @@ ReduceFn pick_reduce(int mode, int dc) {
 // steps (one per KT slice of each dense product, half a step per identity
 // product).  Tiles whose cost exceeds a target are cut between products into
 // several items that write partial tiles; the target is chosen so that the
-// launch has at least ~16k items (enough to fill 256 CUs several times over)
-// but never below 64 steps.  Items are issued heaviest first (longest
+// launch has at least ~min_items items (16k work-groups fill 256 CUs several
+// times over; the wave kernels take four items per work-group and ask for
+// 64k) but never below min_steps (64: a floor of 16 for the wave kernels
+// added reduction work and gained nothing).  Items are issued heaviest first (longest
 // processing time first), which bounds the tail of the launch.
 void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int kt, int bm, int bn,
-                std::vector<WorkItem>& items, std::vector<RedItem>& reds, long long& nslots) {
+                double min_items, double min_steps, std::vector<WorkItem>& items, std::vector<RedItem>& reds,
+                long long& nslots) {
   std::vector<double> pcost(terms.size());
   for (size_t t = 0; t < terms.size(); ++t)
     pcost[t] = (terms[t].flags & (TF_IDENT_A | TF_IDENT_B)) ? 0.5 : (double)((terms[t].k + kt - 1) / kt);
@@ -1521,7 +1524,7 @@ void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& ter
     for (int64_t t = J.tbeg; t < J.tend; ++t) c += pcost[t];
     total += c * (double)((J.m + bm - 1) / bm) * (double)((J.n + bn - 1) / bn);
   }
-  double target = std::max(64.0, total / 16384.0);
+  double target = std::max(min_steps, total / min_items);
   // DMRG_SPLIT_STEPS overrides the target (tuning and tests of the split path)
   if (const char* e = std::getenv("DMRG_SPLIT_STEPS")) {
     const double v = std::atof(e);
@@ -1716,7 +1719,7 @@ class HipExec : public Executor {
     if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
     std::vector<WorkItem> items;
     std::vector<RedItem> reds;
-    plan_items(jobs, terms, P->kt, P->bm, P->bn, items, reds, P->nslots);
+    plan_items(jobs, terms, P->kt, P->bm, P->bn, P->wave ? 65536.0 : 16384.0, 64.0, items, reds, P->nslots);
     P->nitems = (long long)items.size();
     P->nreds = (long long)reds.size();
     if (P->nreds) pick_reduce(P->mode, dc);

@@ -9,8 +9,9 @@ H*psi (bench.py times one BF16 and one FP64 H*psi per step).
 `traffic` reads two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
 `bench.py --copy-calibration MIB`.  Each counter is scaled by what it reads
 for the plain device copy of known size (bytes copied / counter bytes), and
-the HBM bytes of the dominant kernel over the last BF16 H*psi of the run
-(HPSI_LAUNCHES launches of gemm_bf16_padded) are written to OUT.json together
+the HBM bytes of the dominant kernels -- the BF16 grouped GEMMs
+gemm_bf16_padded and gemm_bf16_wave -- over the last BF16 H*psi of the run
+(its last HPSI_LAUNCHES dispatches of them) are written to OUT.json together
 with the SHA-256 of the kernel source, so that a later reader can tell whether
 the figures still describe the kernel.
 """
@@ -32,8 +33,12 @@ def source_sha256() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
+BF16_GEMMS = ("gemm_bf16_padded", "gemm_bf16_wave")
+
+
 def short_name(name: str) -> str:
-    m = re.search(r"(gemm_kernel|gemm_bf16_padded|reduce_kernel|convert_kernel|pack_kernel)<([^>]*)>", name)
+    m = re.search(r"(gemm_kernel|gemm_bf16_padded|gemm_bf16_wave|gemm_f64_wave|reduce_kernel|convert_kernel|pack_kernel)"
+                  r"<([^>]*)>", name)
     if m:
         return f"{m.group(1)}<{m.group(2)}>"
     return name.split("(")[0][:60]
@@ -57,9 +62,9 @@ def trace(d: str) -> None:
         print(f"| {k} | {n} | {ms:.1f} | {ms / n * 1e3:.1f} |")
     # last BF16 H*psi: the final run of consecutive gemm_bf16_padded / reduce launches
     names = [short_name(r["Kernel_Name"]) for r in rows]
-    last = max(i for i, n in enumerate(names) if n.startswith("gemm_bf16_padded"))
+    last = max(i for i, n in enumerate(names) if n.startswith(BF16_GEMMS))
     first = last
-    while first > 0 and (names[first - 1].startswith("gemm_bf16_padded") or names[first - 1].startswith("reduce_kernel<1")):
+    while first > 0 and (names[first - 1].startswith(BF16_GEMMS) or names[first - 1].startswith("reduce_kernel<1")):
         first -= 1
     grp = defaultdict(lambda: [0, 0.0, 0])
     for r in rows[first:last + 1]:
@@ -83,12 +88,12 @@ def _counter(rows, kernel_pred):
 
 
 def traffic(fetch_dir: str, write_dir: str, launches: int) -> dict:
-    res = {"kernel": "gemm_bf16_padded", "source_sha256": source_sha256(), "launches": launches}
+    res = {"kernel": "+".join(BF16_GEMMS), "source_sha256": source_sha256(), "launches": launches}
     for name, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _rows(os.path.join(d, "run_counter_collection.csv"))
         # the calibration copy is the largest copyBuffer dispatch of the run
         counted = max(_counter(rows, lambda n: "copyBuffer" in n))
-        gem = _counter(rows, lambda n: "gemm_bf16_padded" in n)
+        gem = _counter(rows, lambda n: any(k in n for k in BF16_GEMMS))
         res[name] = {"copy_counter_bytes": counted, "gemm_counter_bytes_last_hpsi": sum(gem[-launches:])}
     return res
 
