@@ -205,6 +205,22 @@ int dmrg_batch_create(dmrg_ctx *const *ctxs, int count, int prec, dmrg_batch **o
 int dmrg_batch_hpsi(dmrg_batch *b, const void *const *d_in, void *const *d_out);
 void dmrg_batch_destroy(dmrg_batch *b);
 
+/* Batched Davidson: dmrg_davidson_step on every context of the batch at once
+ * (each with its own opts: precision, tolerance, refinement), with the
+ * matvecs of all instances gathered into the batch's merged launches.  Each
+ * context's solver runs on a host thread of its own; whenever every
+ * unfinished solver waits for a matvec, one merged H*psi per requested
+ * precision serves them all (instances that already finished are computed
+ * on stale inputs and ignored).  psi[i]: host start vector / result of
+ * context i (n_elems, as dmrg_davidson_step); energy, resid, status and the
+ * (nullable) matvec counts are arrays of batch size.  status[i] is the code
+ * dmrg_davidson_step would return for instance i; the call returns OK if all
+ * are OK, else the first non-NOCONV error, else NOCONV.  The contexts must
+ * not be used by other threads during the call.  Errors: ARG (as
+ * dmrg_batch_hpsi), HIP, NOCONV, NONFINITE. */
+int dmrg_batch_davidson(dmrg_batch *b, double *const *psi, double *energy, double *resid, int *n_matvec_lowprec,
+                        int *n_matvec_fp64, int *status);
+
 const char *dmrg_last_error(void);
 void dmrg_destroy(dmrg_ctx *c);
 

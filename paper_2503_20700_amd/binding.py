@@ -79,6 +79,7 @@ def load(path=None):
         "dmrg_batch_create": (I, [ct.POINTER(P), I, I, ct.POINTER(P)]),
         "dmrg_batch_hpsi": (I, [P, ct.POINTER(P), ct.POINTER(P)]),
         "dmrg_batch_destroy": (V, [P]),
+        "dmrg_batch_davidson": (I, [P, ct.POINTER(dp), dp, dp, ip, ip, ip]),
         "dmrg_last_error": (ct.c_char_p, []),
         "dmrg_destroy": (V, [P]),
     }
@@ -94,7 +95,7 @@ def exported_symbols():
     return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_heff_diag",
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_truncate_dbss", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
             "dmrg_kernel_timing", "dmrg_current_block", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
-            "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_last_error", "dmrg_destroy"]
+            "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_batch_davidson", "dmrg_last_error", "dmrg_destroy"]
 
 
 def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ident_b=False, alpha=1.0, beta=0.0,
@@ -285,6 +286,26 @@ class HpsiBatch:
         rc = self.lib.dmrg_batch_hpsi(self._h, a, b)
         if rc != 0:
             raise DMRGError(rc, self.lib.dmrg_last_error().decode())
+
+    def davidson(self, psis):
+        """dmrg_davidson_step on every context at once, matvecs batched.
+        psis: host start vectors (zero: random start).  Returns one dict per
+        context, like DMRG.davidson, plus its status code."""
+        n = len(self.contexts)
+        if len(psis) != n:
+            raise ValueError("one start vector per context")
+        if not self._h:
+            raise DMRGError(-1, "batch is closed")
+        vecs = [np.ascontiguousarray(p, dtype=np.float64).copy() for p in psis]
+        arr = (ct.POINTER(ct.c_double) * n)(*[_dp(v) for v in vecs])
+        e, r = np.zeros(n), np.zeros(n)
+        nlo, nhi, st = (np.zeros(n, dtype=np.int32) for _ in range(3))
+        ip_ = lambda a: a.ctypes.data_as(ct.POINTER(ct.c_int))
+        rc = self.lib.dmrg_batch_davidson(self._h, arr, _dp(e), _dp(r), ip_(nlo), ip_(nhi), ip_(st))
+        if rc not in (0, -6):
+            raise DMRGError(rc, self.lib.dmrg_last_error().decode())
+        return [dict(psi=v, energy=float(e[i]), resid=float(r[i]), n_lo=int(nlo[i]), n_fp64=int(nhi[i]),
+                     converged=int(st[i]) == 0, status=int(st[i])) for i, v in enumerate(vecs)]
 
     def close(self):
         if self._h:

@@ -93,6 +93,10 @@ double* P(dmrg_ctx* c, int b) { return (double*)c->C->ptr(b); }
 
 // y = H x for device FP64 vectors via the plan buffers.
 void matvec(dmrg_ctx* c, const double* x, double* y, int prec, int64_t n) {
+  if (c->mv_hook) {
+    c->mv_hook(x, y, prec);
+    return;
+  }
   c->ex->copy_d2d(c->C->ptr(c->b_in), x, (size_t)n * 8);
   c->hpsi_device(prec);
   c->ex->copy_d2d(y, c->C->ptr(c->b_out), (size_t)n * 8);
@@ -286,6 +290,10 @@ Workspace workspace(dmrg_ctx* c, int64_t n, int mmax) {
 extern "C" int dmrg_davidson_step(dmrg_ctx* c, int k, double* psi, double* energy, double* resid, int* nlo, int* nhi) {
   if (!c || !psi || !energy || !resid) return dmrg_fail(DMRG_ERR_ARG, "dmrg_davidson_step: null argument");
   if (!c->C->Lblk || k != c->C->k) return dmrg_fail(DMRG_ERR_ARG, "dmrg_davidson_step: no MPS loaded at this k");
+  return davidson_core(c, psi, energy, resid, nlo, nhi);
+}
+
+int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* nlo, int* nhi) {
   try {
     c->ensure_plan();
     const int64_t n = c->plan->lay.size;

@@ -1,6 +1,7 @@
 // Per-context state behind the C ABI: executor, planner context, the H*psi
 // plan of the current two-site block and its device buffers.
 #pragma once
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -10,6 +11,11 @@
 
 // Record the thread-local error message returned by dmrg_last_error().
 int dmrg_fail(int code, const std::string& msg);
+
+struct dmrg_ctx;
+// The Davidson solve of dmrg_davidson_step at the context's current block
+// (argument checks done by the caller); returns a dmrg error code.
+int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* nlo, int* nhi);
 
 // psi_in, psi_out, X, ones, diag and padded-psi_in placeholders used by the
 // H*psi task lists
@@ -23,6 +29,10 @@ struct dmrg_ctx {
   int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1, b_inp = -1;
   void* d_pidx = nullptr;  // padded psi index -> caller index (int32, -1 = padding)
   long long plan_serial = 0;  // bumped whenever a new H*psi plan is made
+  // When set, the Davidson's matvecs y = H x (device FP64 vectors of the
+  // plan's length) go through this instead of hpsi_device: the batched
+  // Davidson gathers them into one grouped launch for several contexts.
+  std::function<void(const double* x, double* y, int prec)> mv_hook;
   struct Prepared {
     std::vector<void*> L, R;
     bool ready = false;

@@ -150,3 +150,50 @@ def test_batch_bf16_each_kernel(instances, wave, monkeypatch):
     first, _ = _run_batch(instances, 2)
     for x, y in zip(instances, first):
         assert np.abs(y - x["ref"]).max() < 2.0 ** -8 * 8 * np.abs(x["ref"]).max()
+
+
+@pytest.mark.parametrize("prec,jd", [(0, 0), (2, 10)], ids=["fp64", "bf16+jd"])
+def test_batch_davidson_matches_single_and_dense(prec, jd):
+    # dmrg_batch_davidson: every instance's solve, with its matvecs gathered
+    # into the merged launches, converges to the same eigenpair as its own
+    # dmrg_davidson_step; the smallest instance also against the dense
+    # lowest eigenvalue of the oracle's H_eff.
+    from paper_2503_20700_amd.binding import DMRG, HpsiBatch
+    singles, batched, starts, dense_case = [], [], [], None
+    for n, ne, ts, d, k, seed, budget in INSTANCES:
+        h, g, _ = small_cas(n, seed)
+        mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+        psi, lay = random_psi(mps, seed=seed + 200)
+        if dense_case is None:
+            dense_case = np.linalg.eigvalsh(heff.HeffDefinition(h, g, mps, lay).dense())[0]
+        for lst in (singles, batched):
+            dm = DMRG(h, g, ne, ts, work_budget_elems=budget, hpsi_prec=prec, davidson_jd_inner=jd,
+                      davidson_max_iter=300)
+            bs, cnt = mps.bond_table()
+            dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+            lst.append(dm)
+        starts.append(psi)
+    print(f"[batch davidson] prec={prec} jd={jd}", flush=True)
+    ref = [dm.davidson(p) for dm, p in zip(singles, starts)]
+    b = HpsiBatch(batched, prec)
+    got = b.davidson(starts)
+    b.close()
+    for r, s in zip(got, ref):
+        assert r["converged"] and s["converged"]
+        assert r["resid"] <= 1e-7
+        assert abs(r["energy"] - s["energy"]) < 1e-9
+        assert abs(abs(r["psi"] @ s["psi"]) - 1.0) < 1e-8
+    assert abs(got[0]["energy"] - dense_case) < 1e-9
+
+
+def test_batch_davidson_rejects_changed_context():
+    from paper_2503_20700_amd.binding import DMRGError, HpsiBatch
+    a = _make(6, 6, 0, 16, 2, 2, 0)
+    c = _make(7, 7, 1, 16, 2, 3, 0)
+    b = HpsiBatch([a["dm"], c["dm"]], 0)
+    bs, cnt = c["mps"].bond_table()
+    c["dm"].set_mps(2, bs, cnt, c["mps"].site_blocks_flat())
+    with pytest.raises(DMRGError) as e:
+        b.davidson([a["psi"], c["psi"]])
+    assert e.value.code == -1
+    b.close()
