@@ -158,6 +158,8 @@ def main():
                     help="CG steps of the Jacobi-Davidson refinement (0: plain FP64 Davidson refinement)")
     ap.add_argument("--x-budget", type=int, default=0, metavar="ELEMS",
                     help="cap on the X intermediates of one H*psi chunk (elements; 0: library default)")
+    ap.add_argument("--graph", action="store_true",
+                    help="batch48: record each context's H*psi as a HIP graph and replay it (hpsi_graph)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -344,7 +346,7 @@ def batch_main(args):
         mps = random_mps(w["n"], w["N"], w["two_s"], w["D"], k=w["k"], seed=w["seed"])
         psi, _ = random_psi(mps, seed=w["seed"] + 1)
         dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=BF16, davidson_jd_inner=args.jd_inner,
-                  davidson_max_iter=300)
+                  davidson_max_iter=300, hpsi_graph=args.graph)
         bs, cnt = mps.bond_table()
         dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())
         _, f = dm.hpsi(psi, FP64)  # plans the task lists
@@ -441,7 +443,8 @@ def batch_main(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "48 instances: CAS(n,n) with n uniform on 10..24, 2S = n mod 2, D uniform on "
                                "{64,128,256,512}, centre two-site block, small-CAS integrals (naux = 4n)",
-                   "instances": [[w["n"], w["two_s"], w["D"], w["psi_len"]] for w in insts]},
+                   "instances": [[w["n"], w["two_s"], w["D"], w["psi_len"]] for w in insts],
+                   "hpsi_graph": bool(args.graph)},
         "roofline": {"bound": "mfma", "achieved": kt, "peak": PEAK["bf16"], "unit": "TFLOP/s",
                      "frac": kt / PEAK["bf16"] if kt else None, "traffic": None},
         "cpu_baseline": None,

@@ -83,6 +83,11 @@ typedef struct {
                                   hpsi_prec                                        */
   int davidson_lowprec_iter;   /* iterations of the low-precision Davidson phase
                                   before refinement; -1: davidson_max_iter, 0: none */
+  int hpsi_graph;              /* 1: record each precision's H*psi launch sequence
+                                  as a HIP graph on first use and replay it (less
+                                  host overhead for small blocks); re-recorded when
+                                  the library's scratch moves; not used while
+                                  dmrg_kernel_timing records                       */
 } dmrg_opts;
 
 /* Create a context; copies h (n*n) and g (n^4).  Errors: ARG, SYMMETRY

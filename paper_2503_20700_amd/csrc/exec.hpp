@@ -12,6 +12,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <stdexcept>
 #include <vector>
 
 namespace dmrg {
@@ -115,6 +116,19 @@ class Executor {
   virtual void pack(void* dst, int dt_dst, const double* src, const int* idx, size_t n) = 0;
   // element-wise precision conversion of n values
   virtual void convert(void* dst, int dt_dst, const void* src, int dt_src, size_t n) = 0;
+  // ---- optional: record the calls made between capture_begin and
+  // capture_end (no allocation, synchronisation or prepare in between) into a
+  // graph that replay() re-issues on the stream.  A graph refers to the
+  // executor's shared scratch, so it is valid only while scratch_generation()
+  // is unchanged.  Timing (timing(true)) is not recorded.
+  virtual bool graphs() const { return false; }
+  virtual void capture_begin() { throw std::runtime_error("executor: no graph capture"); }
+  virtual void* capture_end() { throw std::runtime_error("executor: no graph capture"); }
+  virtual void capture_abort() {}
+  virtual void replay(void* graph) { (void)graph; throw std::runtime_error("executor: no graph capture"); }
+  virtual void drop_graph(void* graph) { (void)graph; }
+  virtual long long scratch_generation() const { return 0; }
+  virtual bool timing_on() const { return false; }
 };
 
 // The product executor (HIP, gfx950).

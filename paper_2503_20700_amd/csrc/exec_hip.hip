@@ -1147,6 +1147,16 @@ __global__ void pack_kernel(void* dst, const double* __restrict__ src, const int
   }
 }
 
+// bytes of zeros: 16-byte vectors, then the tail (stream-ordered clear that a
+// graph may record, unlike a memset node)
+__global__ void fill_zero_kernel(unsigned char* p, long long nbytes) {
+  const long long nv = nbytes >> 4;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv; i += (long long)gridDim.x * blockDim.x)
+    ((uint4*)p)[i] = make_uint4(0, 0, 0, 0);
+  const long long t = (nv << 4) + blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t < nbytes && blockIdx.x == 0 && threadIdx.x < 16) p[t] = 0;
+}
+
 template <int DS, int DD>
 __global__ void convert_kernel(void* dst, const void* src, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -1680,8 +1690,45 @@ class HipExec : public Executor {
     HIP_OK(hipStreamSynchronize(stream_));
   }
   void zero(void* p, size_t b) override {
-    if (b) HIP_OK(hipMemsetAsync(p, 0, b, stream_));
+    if (!b) return;
+    if (capturing_) {
+      // the buffers cleared here are hipMalloc'ed, so 16-byte aligned
+      if ((uintptr_t)p & 15) throw std::runtime_error("executor: unaligned clear in a captured graph");
+      const unsigned grid = (unsigned)std::min<size_t>((b / 16 + 255) / 256 + 1, 65536);
+      hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(256), 0, stream_, (unsigned char*)p, (long long)b);
+      HIP_OK(hipGetLastError());
+    } else {
+      HIP_OK(hipMemsetAsync(p, 0, b, stream_));
+    }
   }
+  bool graphs() const override { return true; }
+  void capture_begin() override {
+    HIP_OK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+    capturing_ = true;
+  }
+  void* capture_end() override {
+    capturing_ = false;
+    hipGraph_t g = nullptr;
+    HIP_OK(hipStreamEndCapture(stream_, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t r = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_OK(r);
+    return (void*)e;
+  }
+  void capture_abort() override {
+    if (!capturing_) return;
+    capturing_ = false;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(stream_, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+  }
+  void replay(void* e) override { HIP_OK(hipGraphLaunch((hipGraphExec_t)e, stream_)); }
+  void drop_graph(void* e) override {
+    if (e) (void)hipGraphExecDestroy((hipGraphExec_t)e);
+  }
+  long long scratch_generation() const override { return part_gen_; }
+  bool timing_on() const override { return timing_; }
   void copy_d2d(void* d, const void* s, size_t b) override {
     if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, stream_));
   }
@@ -1743,6 +1790,7 @@ class HipExec : public Executor {
       part_bytes_ = 0;
       part_ = alloc(need);
       part_bytes_ = need;
+      ++part_gen_;  // graphs recorded against the old buffer are stale
     }
     return P;
   }
@@ -1975,6 +2023,8 @@ class HipExec : public Executor {
   double* dot_out_ = nullptr;
   hipStream_t stream_ = nullptr;
   bool timing_ = false;
+  bool capturing_ = false;  // between capture_begin and capture_end
+  long long part_gen_ = 0;  // bumped when part_ is reallocated
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events_;
 };
 

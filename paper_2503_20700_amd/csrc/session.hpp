@@ -36,6 +36,8 @@ struct dmrg_ctx {
   struct Prepared {
     std::vector<void*> L, R;
     bool ready = false;
+    void* graph = nullptr;     // recorded H*psi sequence (opts.hpsi_graph)
+    long long graph_gen = -1;  // executor scratch generation it was recorded at
   };
   Prepared prep[3];
   // cut spectrum of the last truncation
@@ -58,6 +60,9 @@ struct dmrg_ctx {
 
   void reset_plan() {
     for (auto& p : prep) {
+      ex->drop_graph(p.graph);
+      p.graph = nullptr;
+      p.graph_gen = -1;
       for (void* h : p.L) ex->drop(h);
       for (void* h : p.R) ex->drop(h);
       p.L.clear();
@@ -156,9 +161,8 @@ struct dmrg_ctx {
     P.ready = true;
   }
 
-  // psi_out = H psi_in on the device buffers b_in / b_out (FP64 masters).
-  void hpsi_device(int prec) {
-    prepare(prec);
+  // The launches of psi_out = H psi_in on b_in / b_out (prepared already).
+  void enqueue_hpsi(int prec) {
     const int64_t n = plan->lay.size;
     const int od = op_dt(prec), outd = out_dt(prec);
     ex->pack(C->ptr(b_inp, od), od, (const double*)C->ptr(b_in), (const int*)d_pidx, (size_t)plan->lay.psize);
@@ -169,6 +173,34 @@ struct dmrg_ctx {
       ex->run(P.R[i]);
     }
     if (outd != dmrg::DT_F64) ex->convert(C->ptr(b_out), dmrg::DT_F64, C->ptr(b_out, outd), outd, (size_t)n);
+  }
+
+  // psi_out = H psi_in on the device buffers b_in / b_out (FP64 masters).
+  // With opts.hpsi_graph the launch sequence is recorded once per precision
+  // and replayed (re-recorded when the executor's scratch moved), except
+  // while kernel timing is on.
+  void hpsi_device(int prec) {
+    prepare(prec);
+    Prepared& P = prep[prec];
+    if (opts.hpsi_graph && ex->graphs() && !ex->timing_on()) {
+      if (!P.graph || P.graph_gen != ex->scratch_generation()) {
+        ex->drop_graph(P.graph);
+        P.graph = nullptr;
+        const long long gen = ex->scratch_generation();
+        ex->capture_begin();
+        try {
+          enqueue_hpsi(prec);
+        } catch (...) {
+          ex->capture_abort();
+          throw;
+        }
+        P.graph = ex->capture_end();
+        P.graph_gen = gen;
+      }
+      ex->replay(P.graph);
+    } else {
+      enqueue_hpsi(prec);
+    }
     ex->sync();
   }
 };

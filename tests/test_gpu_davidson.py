@@ -62,3 +62,25 @@ def test_davidson_jacobi_davidson_refinement(prec, lowprec_iter, case):
     assert abs(r["energy"] - exact) <= 1e-6
     assert np.linalg.norm(hd @ r["psi"] - exact * r["psi"]) < 1e-6
     assert r["n_lo"] > 0
+
+
+def test_davidson_with_hpsi_graph_equals_eager():
+    # the whole mixed-precision Davidson with recorded H*psi graphs gives the
+    # eager run's eigenpair and matvec counts exactly
+    from paper_2503_20700_amd.binding import DMRG
+    from synth.integrals import small_cas
+    from synth.mps import random_mps, random_psi
+    n, ne, ts, d, k, seed = 8, 8, 0, 64, 3, 0
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    bs, cnt = mps.bond_table()
+    out = []
+    for graph in (False, True):
+        dm = DMRG(h, g, ne, ts, hpsi_prec=2, davidson_jd_inner=10, davidson_max_iter=300, hpsi_graph=graph)
+        dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+        out.append(dm.davidson(psi))
+    a, b = out
+    assert a["converged"] and b["converged"]
+    assert a["energy"] == b["energy"] and (a["n_lo"], a["n_fp64"]) == (b["n_lo"], b["n_fp64"])
+    assert np.array_equal(a["psi"], b["psi"])

@@ -139,3 +139,60 @@ def test_hpsi_fp64_each_kernel(case, wave, monkeypatch):
     assert np.abs(y - ref).max() < 1e-10 * np.abs(ref).max()
     y2, _ = dm.hpsi(psi)
     assert np.array_equal(y, y2)
+
+
+def test_hpsi_graph_replays_equal_eager():
+    # opts.hpsi_graph: the H*psi launch sequence is recorded once per
+    # precision and replayed.  Every replay -- with other work and device
+    # synchronisations in between, across precisions, and after the shared
+    # scratch buffer has moved (re-recorded) -- equals the eager result bit
+    # for bit.
+    from paper_2503_20700_amd.binding import DMRG
+    case = (10, 10, 0, 40, 4, 6)
+    n, ne, ts, d, k, seed = case
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    bs, cnt = mps.bond_table()
+    eager = DMRG(h, g, ne, ts)
+    graph = DMRG(h, g, ne, ts, hpsi_graph=True)
+    for dm in (eager, graph):
+        dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+    rng = np.random.default_rng(5)
+    vecs = [psi] + [rng.normal(size=psi.size) for _ in range(3)]
+    for rep in range(3):
+        for prec in (0, 2, 1):
+            for v in vecs:
+                print(f"[hpsi graph] rep={rep} prec={prec}", flush=True)
+                want, _ = eager.hpsi(v, prec)
+                got, _ = graph.hpsi(v, prec)
+                assert np.array_equal(got, want)
+        # eager work on the graph context's own stream between replays
+        graph.heff_diag(psi.size)
+    ref = heff.hpsi(h, g, mps, lay, psi)
+    got, _ = graph.hpsi(psi, 0)
+    assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("split", ["", "1"], ids=["default", "split1"])
+def test_hpsi_graph_rerecords_after_scratch_moves(split, monkeypatch):
+    # A later launch plan that needs a larger partial-tile buffer moves the
+    # executor's scratch; the recorded graph must then be re-recorded, not
+    # replayed against the freed buffer.
+    from paper_2503_20700_amd.binding import DMRG
+    case = (8, 8, 0, 64, 3, 0)
+    n, ne, ts, d, k, seed = case
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    bs, cnt = mps.bond_table()
+    dm = DMRG(h, g, ne, ts, hpsi_graph=True)
+    dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+    first, _ = dm.hpsi(psi, 0)             # recorded with the current scratch
+    if split:
+        monkeypatch.setenv("DMRG_SPLIT_STEPS", split)
+    dm.hpsi(psi, 2)                          # BF16 plan, with every tile split: more scratch
+    again, _ = dm.hpsi(psi, 0)             # must re-record if the scratch moved
+    assert np.array_equal(first, again)
+    ref = heff.hpsi(h, g, mps, lay, psi)
+    assert np.abs(again - ref).max() < 1e-10 * np.abs(ref).max()
