@@ -70,7 +70,8 @@ typedef struct {
   int davidson_max_iter;       /* outer iterations per davidson_step                 */
   int davidson_max_subspace;   /* basis size before restart                          */
   int hpsi_prec;               /* dmrg_prec used for the bulk matvecs in Davidson    */
-  long long work_budget_elems; /* cap on intermediate buffers (elements), 0: default */
+  long long work_budget_elems; /* cap on intermediate buffers (elements) per H*psi
+                                  chunk; 0: default 2^32                           */
   int keep_blocks;             /* 1: keep the operator blocks of every bond that
                                   dmrg_set_mps builds, so dmrg_truncate can move
                                   the two-site block (memory grows with n)        */

@@ -55,7 +55,10 @@ struct dmrg_ctx {
   }
 
   int64_t budget() const {
-    return opts.work_budget_elems > 0 ? (int64_t)opts.work_budget_elems : ((int64_t)1 << 30);
+    // default 2^32 elements of X per chunk: 46 chunks at CAS(82,82) D=4096
+    // (8.6 GB in BF16, 34 GB in FP64); 2^30 gave 182 launches and 3 % more
+    // time, 2^33 and 2^34 longer launch tails
+    return opts.work_budget_elems > 0 ? (int64_t)opts.work_budget_elems : ((int64_t)1 << 32);
   }
 
   void reset_plan() {
