@@ -115,8 +115,17 @@ int dmrg_psi_layout(dmrg_ctx *c, int k, long long *n_superblocks, long long *des
  * products, identities excluded). */
 int dmrg_hpsi(dmrg_ctx *c, int k, const double *psi_in, double *psi_out, int prec, double *flops_out);
 
-/* Same on device buffers (FP64, n_elems each), on the library's stream. */
+/* Same on device buffers (FP64, n_elems each), on the library's stream; the
+ * copy into d_out may still be queued on return (synchronise the device
+ * before reading it). */
 int dmrg_hpsi_dev(dmrg_ctx *c, int k, const void *d_in, void *d_out, int prec);
+
+/* Same, ordered with the caller's HIP stream hip_stream (a hipStream_t;
+ * NULL = the null stream): the product starts after all work queued on
+ * hip_stream before the call (which may still be producing d_in), and work
+ * queued on hip_stream after the call runs after d_out is written.  Neither
+ * side is host-synchronised for this ordering.  Errors as dmrg_hpsi_dev. */
+int dmrg_hpsi_dev_stream(dmrg_ctx *c, int k, const void *d_in, void *d_out, int prec, void *hip_stream);
 
 /* Diagonal of H_eff at the current block (host, n_elems). */
 int dmrg_heff_diag(dmrg_ctx *c, int k, double *diag);

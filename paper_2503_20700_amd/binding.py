@@ -65,6 +65,7 @@ def load(path=None):
         "dmrg_psi_layout": (I, [P, I, llp, llp, llp]),
         "dmrg_hpsi": (I, [P, I, dp, dp, I, dp]),
         "dmrg_hpsi_dev": (I, [P, I, P, P, I]),
+        "dmrg_hpsi_dev_stream": (I, [P, I, P, P, I, P]),
         "dmrg_heff_diag": (I, [P, I, dp]),
         "dmrg_davidson_step": (I, [P, I, dp, dp, dp, ip, ip]),
         "dmrg_truncate": (I, [P, I, dp, I, I, D, dp, ip]),
@@ -92,7 +93,8 @@ def load(path=None):
 
 
 def exported_symbols():
-    return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_heff_diag",
+    return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_hpsi_dev_stream",
+            "dmrg_heff_diag",
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_truncate_dbss", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
             "dmrg_kernel_timing", "dmrg_current_block", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
             "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_batch_davidson", "dmrg_last_error", "dmrg_destroy"]
@@ -190,8 +192,15 @@ class DMRG:
         self._check(self.lib.dmrg_hpsi(self._h, self.k, _dp(psi), _dp(out), prec, ct.byref(fl)))
         return out, fl.value
 
-    def hpsi_dev(self, d_in, d_out, prec=FP64):
-        self._check(self.lib.dmrg_hpsi_dev(self._h, self.k, ct.c_void_p(d_in), ct.c_void_p(d_out), prec))
+    def hpsi_dev(self, d_in, d_out, prec=FP64, stream=None):
+        """d_out = H d_in on device FP64 buffers.  stream: a HIP stream handle
+        (e.g. torch.cuda.current_stream().cuda_stream) to order the product
+        with; without it the caller synchronises the device itself."""
+        if stream is None:
+            self._check(self.lib.dmrg_hpsi_dev(self._h, self.k, ct.c_void_p(d_in), ct.c_void_p(d_out), prec))
+        else:
+            self._check(self.lib.dmrg_hpsi_dev_stream(self._h, self.k, ct.c_void_p(d_in), ct.c_void_p(d_out), prec,
+                                                      ct.c_void_p(stream)))
 
     def heff_diag(self, size):
         out = np.empty(size)

@@ -239,6 +239,24 @@ extern "C" int dmrg_hpsi_dev(dmrg_ctx* c, int k, const void* din, void* dout, in
   }
 }
 
+extern "C" int dmrg_hpsi_dev_stream(dmrg_ctx* c, int k, const void* din, void* dout, int prec, void* hip_stream) {
+  if (!c || !din || !dout) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_stream: null argument");
+  if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_stream: no MPS loaded at this k");
+  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_stream: bad precision");
+  try {
+    c->ensure_plan();
+    const int64_t n = c->plan->lay.size;
+    c->ex->wait_for(hip_stream);  // d_in may still be written by the caller's queued work
+    c->ex->copy_d2d(c->C->ptr(c->b_in), din, (size_t)n * 8);
+    c->hpsi_device(prec);
+    c->ex->copy_d2d(dout, c->C->ptr(c->b_out), (size_t)n * 8);
+    c->ex->signal(hip_stream);  // the caller's later work on the stream sees d_out
+    return DMRG_OK;
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_hpsi_dev_stream: ") + e.what());
+  }
+}
+
 extern "C" int dmrg_heff_diag(dmrg_ctx* c, int k, double* diag) {
   if (!c || !diag) return fail(DMRG_ERR_ARG, "dmrg_heff_diag: null argument");
   if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_heff_diag: no MPS loaded at this k");

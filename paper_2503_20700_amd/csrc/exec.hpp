@@ -129,6 +129,12 @@ class Executor {
   virtual void drop_graph(void* graph) { (void)graph; }
   virtual long long scratch_generation() const { return 0; }
   virtual bool timing_on() const { return false; }
+  // ---- ordering with a caller's stream (a hipStream_t; nullptr = the null
+  // stream).  wait_for(s): later work of the executor waits for everything
+  // queued on s so far.  signal(s): later work on s waits for everything
+  // queued on the executor's stream so far.  Neither blocks the host.
+  virtual void wait_for(void* stream) { (void)stream; }
+  virtual void signal(void* stream) { (void)stream; }
 };
 
 // The product executor (HIP, gfx950).

@@ -1618,7 +1618,19 @@ class HipExec : public Executor {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
     }
+    for (hipEvent_t e : order_ev_)
+      if (e) (void)hipEventDestroy(e);
     if (stream_) (void)hipStreamDestroy(stream_);
+  }
+  void wait_for(void* s) override {
+    hipEvent_t e = order_event(0);
+    HIP_OK(hipEventRecord(e, (hipStream_t)s));
+    HIP_OK(hipStreamWaitEvent(stream_, e, 0));
+  }
+  void signal(void* s) override {
+    hipEvent_t e = order_event(1);
+    HIP_OK(hipEventRecord(e, stream_));
+    HIP_OK(hipStreamWaitEvent((hipStream_t)s, e, 0));
   }
   // Device memory is cached: released blocks go to a free list keyed by size
   // and are handed out again for requests they fit (within 1/8 slack), so a
@@ -2023,6 +2035,11 @@ class HipExec : public Executor {
   double* dot_out_ = nullptr;
   hipStream_t stream_ = nullptr;
   bool timing_ = false;
+  hipEvent_t order_ev_[2] = {nullptr, nullptr};  // wait_for / signal
+  hipEvent_t order_event(int i) {
+    if (!order_ev_[i]) HIP_OK(hipEventCreateWithFlags(&order_ev_[i], hipEventDisableTiming));
+    return order_ev_[i];
+  }
   bool capturing_ = false;  // between capture_begin and capture_end
   long long part_gen_ = 0;  // bumped when part_ is reallocated
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events_;

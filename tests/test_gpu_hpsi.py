@@ -196,3 +196,29 @@ def test_hpsi_graph_rerecords_after_scratch_moves(split, monkeypatch):
     assert np.array_equal(first, again)
     ref = heff.hpsi(h, g, mps, lay, psi)
     assert np.abs(again - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_hpsi_dev_stream_orders_with_caller_stream():
+    # dmrg_hpsi_dev_stream: the input is written on the caller's stream behind
+    # ~30 ms of queued work, and the output is consumed on that stream right
+    # after the call; with the stream ordering both see the right data
+    # (without it the product would read the zero input, or the consumer NaN).
+    import torch
+    case = (10, 10, 0, 40, 4, 6)
+    h, g, mps, psi, lay, dm = _setup(*case)
+    want, _ = dm.hpsi(psi, 0)
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(psi).to(dev)
+    x = torch.zeros_like(src)
+    y = torch.full_like(src, float("nan"))
+    a = torch.randn(4096, 4096, device=dev)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for _ in range(20):
+            a = (a @ a) * 1e-2  # keeps the stream busy before the input exists
+        x.copy_(src)
+        dm.hpsi_dev(x.data_ptr(), y.data_ptr(), 0, stream=s.cuda_stream)
+        z = y * 1.0
+    torch.cuda.synchronize()
+    assert np.array_equal(z.cpu().numpy(), want)
