@@ -158,6 +158,9 @@ def main():
                     help="CG steps of the Jacobi-Davidson refinement (0: plain FP64 Davidson refinement)")
     ap.add_argument("--x-budget", type=int, default=0, metavar="ELEMS",
                     help="cap on the X intermediates of one H*psi chunk (elements; 0: library default)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time a half-sweep from the centre to the right end (operator blocks of every bond "
+                         "kept; fits one GPU for CAS(32,32) D=1024, not for CAS(82,82) D=4096)")
     ap.add_argument("--graph", action="store_true",
                     help="batch48: record each context's H*psi as a HIP graph and replay it (hpsi_graph)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -168,6 +171,9 @@ def main():
         sys.exit(2)
     if args.config == "batch48":
         batch_main(args)
+        return
+    if args.sweep:
+        sweep_main(args)
         return
 
     import torch
@@ -326,6 +332,66 @@ def main():
         "peak_device_bytes": st["peak_bytes"],
     }
     print(json.dumps(out), flush=True)
+
+
+def sweep_main(args):
+    """Half-sweep from the centre block to the right end of the chain: at
+    every two-site block a Davidson solve to the residual 1e-7 (BF16 bulk
+    matvecs, then Jacobi-Davidson FP64 refinement with --jd-inner BF16 CG
+    steps per correction, at most 300 iterations per phase), truncation to D
+    multiplets and growth of the left operator block.  The right blocks of
+    every bond are built once before timing (keep_blocks).  Every block
+    starts from a random vector (no guess is carried across the move)."""
+    import torch
+    from paper_2503_20700_amd.binding import BF16, DMRG
+    from synth.mps import random_mps, random_psi
+
+    w = workload(args.config)
+    mps = random_mps(w["n"], w["N"], w["two_s"], w["D"], k=w["k"], seed=w["seed"])
+    psi, _ = random_psi(mps, seed=w["seed"] + 1)
+    dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=BF16, davidson_max_iter=300,
+              davidson_jd_inner=args.jd_inner, keep_blocks=True)
+    bs, cnt = mps.bond_table()
+    t0 = time.perf_counter()
+    dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())
+    t_env = time.perf_counter() - t0
+    log(f"{w['name']}: operator blocks of every bond built in {t_env:.1f}s")
+    steps = []
+    start = psi
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    while dm.k is not None and 0 <= dm.k <= w["n"] - 2:
+        k = dm.k
+        t0 = time.perf_counter()
+        r = dm.davidson(start)
+        t1 = time.perf_counter()
+        err, kept = dm.truncate(r["psi"], w["D"], 0.0, 1)
+        t2 = time.perf_counter()
+        steps.append({"block": [k, k + 1], "davidson_s": t1 - t0, "truncate_and_grow_s": t2 - t1,
+                      "energy_Eh": r["energy"], "residual": r["resid"], "converged": r["converged"],
+                      "matvecs": [r["n_lo"], r["n_fp64"]],
+                      "trunc_err": err, "d_kept": kept})
+        log(f"block ({k},{k + 1}): {t2 - t0:.2f}s, E {r['energy']:.8f}, residual {r['resid']:.1e}, kept {kept}")
+        _, nel = dm.psi_layout() if dm.k >= 0 else (None, 0)
+        start = np.zeros(nel)  # no guess carried over: a random start at the next block
+    torch.cuda.synchronize()
+    t_sweep = time.perf_counter() - t_start
+    out = {
+        "metric": "half-sweep time, " + w["name"],
+        "value": t_sweep,
+        "unit": "s",
+        "n_gpus": 1, "steps": len(steps), "warmup": 0,
+        "ms_per_step": t_sweep / max(len(steps), 1) * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": w["name"] + ", half-sweep to the right end", "n_orb": w["n"], "D": w["D"],
+                   "first_block": [w["k"], w["k"] + 1],
+                   "davidson": {"residual_target": 1e-7, "max_iter": 300, "jd_inner_cg": args.jd_inner}},
+        "all_converged": all(st["converged"] for st in steps),
+        "setup_s": {"operator_blocks_all_bonds": t_env},
+        "sweep_steps": steps,
+    }
+    print(json.dumps(out), flush=True)
+    dm.close()
 
 
 def batch_main(args):
