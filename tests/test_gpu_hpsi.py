@@ -222,3 +222,27 @@ def test_hpsi_dev_stream_orders_with_caller_stream():
         z = y * 1.0
     torch.cuda.synchronize()
     assert np.array_equal(z.cpu().numpy(), want)
+
+
+EDGE_CASES = [
+    # n, N, 2S, D, k, seed: the degenerate shapes of the method
+    (6, 6, 0, 16, 0, 11),   # two-site block at the left end: left block is the vacuum
+    (6, 6, 0, 16, 4, 12),   # at the right end: right block is the vacuum
+    (7, 7, 1, 20, 5, 13),   # right end, doublet
+    (6, 2, 0, 16, 2, 14),   # two electrons in six orbitals
+    (6, 4, 4, 16, 2, 15),   # high spin, 2S = N
+    (5, 5, 5, 8, 1, 16),    # fully polarised half filling: a one-coefficient space
+    (6, 10, 0, 16, 2, 17),  # two holes in six orbitals
+]
+
+
+@pytest.mark.parametrize("prec,bound", [(0, 1e-10), (1, 2.0 ** -24 * 64), (2, 2.0 ** -8 * 8)],
+                         ids=["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("case", EDGE_CASES, ids=[f"n{c[0]}N{c[1]}S{c[2]}k{c[4]}" for c in EDGE_CASES])
+def test_hpsi_edge_cases_match_oracle(case, prec, bound):
+    print(f"[hpsi edge] case={case} prec={prec}", flush=True)
+    h, g, mps, psi, lay, dm = _setup(*case)
+    y, _ = dm.hpsi(psi, prec)
+    ref = heff.hpsi(h, g, mps, lay, psi)
+    assert np.all(np.isfinite(y))
+    assert np.abs(y - ref).max() <= bound * np.abs(ref).max()
