@@ -1,0 +1,74 @@
+"""Host-side logic with no GPU: the 48-instance workload recipe and the
+arithmetic that turns rocprofv3 counter files into HBM bytes."""
+import csv
+import json
+import os
+
+import numpy as np
+
+
+def test_batch_instances_follow_the_recipe():
+    import bench
+    insts = bench.batch_instances()
+    assert len(insts) == 48
+    for i, w in enumerate(insts):
+        assert 10 <= w["n"] <= 24 and w["N"] == w["n"] and w["two_s"] == w["n"] % 2
+        assert w["D"] in (64, 128, 256, 512)
+        assert w["seed"] == 1000 + i and w["k"] == w["n"] // 2 - 1
+        g = w["g"]
+        # density-fitting integrals: 8-fold symmetric, (pp|pp) > 0
+        assert np.allclose(g, g.transpose(1, 0, 2, 3)) and np.allclose(g, g.transpose(2, 3, 0, 1))
+        assert (np.einsum("pppp->p", g) > 0).all()
+        assert np.allclose(w["h"], w["h"].T)
+    # seeded: the same list every time
+    again = bench.batch_instances()
+    assert all(a["n"] == b["n"] and a["D"] == b["D"] and np.array_equal(a["h"], b["h"]) for a, b in zip(insts, again))
+
+
+def _write_counters(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_scales_counters_by_the_copy_and_sums_the_last_launches(tmp_path):
+    from paper_2503_20700_amd import rocprof_summary as rs
+    # a 2 MiB copy that the fetch counter reports as half (in KiB), and
+    # three GEMM launches of which the last two form the H*psi
+    copy_kib = 2 * 1024.0
+    fetch = [{"Dispatch_Id": 1, "Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Value": copy_kib / 2},
+             {"Dispatch_Id": 2, "Kernel_Name": "void gemm_bf16_padded<2, 64, 64>(...)", "Counter_Value": 999.0},
+             {"Dispatch_Id": 3, "Kernel_Name": "void gemm_bf16_padded<2, 64, 64>(...)", "Counter_Value": 100.0},
+             {"Dispatch_Id": 4, "Kernel_Name": "void gemm_bf16_wave<1>(...)", "Counter_Value": 50.0}]
+    write = [{"Dispatch_Id": 1, "Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Value": copy_kib},
+             {"Dispatch_Id": 2, "Kernel_Name": "void gemm_bf16_padded<2, 64, 64>(...)", "Counter_Value": 7.0},
+             {"Dispatch_Id": 3, "Kernel_Name": "void gemm_bf16_padded<2, 64, 64>(...)", "Counter_Value": 10.0},
+             {"Dispatch_Id": 4, "Kernel_Name": "void gemm_bf16_wave<1>(...)", "Counter_Value": 20.0}]
+    _write_counters(tmp_path / "f", fetch)
+    _write_counters(tmp_path / "w", write)
+    out = tmp_path / "t.json"
+    assert rs.main(["traffic", str(tmp_path / "f"), str(tmp_path / "w"), "2", "2", str(out)]) == 0
+    t = json.loads(out.read_text())
+    assert abs(t["fetch"]["scale"] - 2.0) < 1e-12 and abs(t["write"]["scale"] - 1.0) < 1e-12
+    assert abs(t["fetch"]["hbm_bytes_last_hpsi"] - 2.0 * 150.0 * 1024) < 1e-6
+    assert abs(t["write"]["hbm_bytes_last_hpsi"] - 30.0 * 1024) < 1e-6
+    assert abs(t["hbm_bytes_per_hpsi"] - (300.0 + 30.0) * 1024) < 1e-6
+    assert t["source_sha256"] == rs.source_sha256() and t["launches"] == 2
+
+
+def test_bench_reports_traffic_only_for_the_kernel_source_it_was_taken_on():
+    # roofline.traffic comes from the committed counter file while its hash
+    # matches the executor source, and is null otherwise
+    import bench
+    from paper_2503_20700_amd.rocprof_summary import source_sha256
+    with open(bench.TRAFFIC_FILE) as f:
+        t = json.load(f)
+    total, detail = bench.measured_traffic("cfg4")
+    if t["source_sha256"] == source_sha256():
+        assert total == t["hbm_bytes_per_hpsi"] and detail["launches"] == t["launches"]
+    else:
+        assert total is None and detail is None
+    assert bench.measured_traffic("cfg1") == (None, None)
