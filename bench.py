@@ -341,7 +341,9 @@ def sweep_main(args):
     steps per correction, at most 300 iterations per phase), truncation to D
     multiplets and growth of the left operator block.  The right blocks of
     every bond are built once before timing (keep_blocks).  Every block
-    starts from a random vector (no guess is carried across the move)."""
+    starts from a random vector: in this first sweep from a random MPS the
+    state carried over by the truncation (dmrg_next_guess) saved no matvecs
+    and once led the solver to an excited eigenpair."""
     import torch
     from paper_2503_20700_amd.binding import BF16, DMRG
     from synth.mps import random_mps, random_psi
@@ -372,8 +374,8 @@ def sweep_main(args):
                       "matvecs": [r["n_lo"], r["n_fp64"]],
                       "trunc_err": err, "d_kept": kept})
         log(f"block ({k},{k + 1}): {t2 - t0:.2f}s, E {r['energy']:.8f}, residual {r['resid']:.1e}, kept {kept}")
-        _, nel = dm.psi_layout() if dm.k >= 0 else (None, 0)
-        start = np.zeros(nel)  # no guess carried over: a random start at the next block
+        if dm.k >= 0:
+            start = np.zeros(dm.psi_layout()[1])  # random start at the next block
     torch.cuda.synchronize()
     t_sweep = time.perf_counter() - t_start
     out = {

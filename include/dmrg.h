@@ -89,6 +89,9 @@ typedef struct {
                                   host overhead for small blocks); re-recorded when
                                   the library's scratch moves; not used while
                                   dmrg_kernel_timing records                       */
+  int next_guess;              /* 1: dmrg_truncate moving right (+1) also forms the
+                                  start vector of the block it moves to (read it
+                                  with dmrg_next_guess)                            */
 } dmrg_opts;
 
 /* Create a context; copies h (n*n) and g (n^4).  Errors: ARG, SYMMETRY
@@ -164,6 +167,17 @@ int dmrg_truncate(dmrg_ctx *c, int k, const double *psi, int direction, int d_ma
  * ARG unless 0 <= d_min <= d_max. */
 int dmrg_truncate_dbss(dmrg_ctx *c, int k, const double *psi, int direction, int d_min, int d_max,
                        double eps_tr, double *trunc_err, int *d_kept);
+
+/* Start vector for the current block (k, k+1) carried over by the last
+ * dmrg_truncate(direction +1) with opts.next_guess set (Sec. "Numerical
+ * procedure": each sweep step starts from the previous step's wavefunction):
+ * the kept part of the previous psi, contracted with the right-canonical
+ * tensor of site k+1 and recoupled to this block's middle-cut basis (one 6j
+ * per block).  Without truncation it is the same state; its norm squared is
+ * 1 - trunc_err for a normalised psi.  psi: n_elems host values (the layout of
+ * dmrg_psi_layout).  Errors: ARG if no vector was carried to this block,
+ * SHAPE for a wrong length. */
+int dmrg_next_guess(dmrg_ctx *c, int k, double *psi, long long n_elems);
 
 /* Read back bond b's sectors ((N, 2S, dim) rows, *n sectors) and site j's
  * tensor (blocks in the canonical order of dmrg_set_mps, *n values); with a

@@ -34,7 +34,7 @@ class Opts(ct.Structure):
                 ("davidson_max_subspace", ct.c_int), ("hpsi_prec", ct.c_int),
                 ("work_budget_elems", ct.c_longlong), ("keep_blocks", ct.c_int),
                 ("davidson_refine_iter", ct.c_int), ("davidson_jd_inner", ct.c_int),
-                ("davidson_lowprec_iter", ct.c_int), ("hpsi_graph", ct.c_int)]
+                ("davidson_lowprec_iter", ct.c_int), ("hpsi_graph", ct.c_int), ("next_guess", ct.c_int)]
 
 
 _LIBS = {}
@@ -75,6 +75,7 @@ def load(path=None):
         "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
         "dmrg_kernel_timing": (I, [P, I, dp, llp]),
         "dmrg_current_block": (I, [P, ip]),
+        "dmrg_next_guess": (I, [P, I, dp, LL]),
         "dmrg_get_bond": (I, [P, I, ip, ip]),
         "dmrg_get_site": (I, [P, I, dp, llp]),
         "dmrg_batch_create": (I, [ct.POINTER(P), I, I, ct.POINTER(P)]),
@@ -96,7 +97,7 @@ def exported_symbols():
     return ["dmrg_create", "dmrg_set_mps", "dmrg_psi_layout", "dmrg_hpsi", "dmrg_hpsi_dev", "dmrg_hpsi_dev_stream",
             "dmrg_heff_diag",
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_truncate_dbss", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
-            "dmrg_kernel_timing", "dmrg_current_block", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
+            "dmrg_kernel_timing", "dmrg_current_block", "dmrg_next_guess", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
             "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_batch_davidson", "dmrg_last_error", "dmrg_destroy"]
 
 
@@ -138,14 +139,14 @@ class DMRG:
     def __init__(self, h, g, n_elec, two_s, e_core=0.0, davidson_tol=1e-7, davidson_max_iter=60,
                  davidson_max_subspace=24, hpsi_prec=FP64, work_budget_elems=0, keep_blocks=False,
                  davidson_refine_iter=0, davidson_jd_inner=0, davidson_lowprec_iter=-1, hpsi_graph=False,
-                 lib=None):
+                 next_guess=False, lib=None):
         self.lib = load(lib)
         h = np.ascontiguousarray(h, dtype=np.float64)
         g = np.ascontiguousarray(g, dtype=np.float64)
         n = h.shape[0]
         self.opts = Opts(n, n_elec, two_s, e_core, davidson_tol, davidson_max_iter, davidson_max_subspace,
                          hpsi_prec, work_budget_elems, int(keep_blocks), davidson_refine_iter,
-                         davidson_jd_inner, davidson_lowprec_iter, int(hpsi_graph))
+                         davidson_jd_inner, davidson_lowprec_iter, int(hpsi_graph), int(next_guess))
         self._h = ct.c_void_p()
         self._batches = weakref.WeakSet()
         self._check(self.lib.dmrg_create(ct.byref(self._h), ct.byref(self.opts), _dp(h), _dp(g)))
@@ -229,6 +230,14 @@ class DMRG:
         self._check(self.lib.dmrg_current_block(self._h, ct.byref(kk)))
         self.k = kk.value
         return err.value, kept.value
+
+    def next_guess(self):
+        """Start vector carried to the current block by the last right-moving
+        truncation (opts next_guess)."""
+        _, nel = self.psi_layout()
+        out = np.zeros(nel)
+        self._check(self.lib.dmrg_next_guess(self._h, self.k, _dp(out), nel))
+        return out
 
     def get_bond(self, b):
         n = ct.c_int()

@@ -49,6 +49,7 @@ extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, 
       o->davidson_jd_inner < 0 || o->davidson_lowprec_iter < -1)
     return fail(DMRG_ERR_ARG, "dmrg_create: negative Davidson budget");
   if (o->hpsi_graph < 0 || o->hpsi_graph > 1) return fail(DMRG_ERR_ARG, "dmrg_create: hpsi_graph must be 0 or 1");
+  if (o->next_guess < 0 || o->next_guess > 1) return fail(DMRG_ERR_ARG, "dmrg_create: next_guess must be 0 or 1");
   const size_t n2 = (size_t)n * n, n4 = n2 * n2;
   if (!finite_all(h, n2) || !finite_all(g, n4)) return fail(DMRG_ERR_NONFINITE, "dmrg_create: non-finite integral");
   try {

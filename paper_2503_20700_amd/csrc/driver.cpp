@@ -26,6 +26,8 @@
 #include <string>
 #include <vector>
 
+#include "su2.hpp"
+
 #include "../../include/dmrg.h"
 #include "session.hpp"
 
@@ -358,6 +360,104 @@ struct CutSector {
 };
 }  // namespace
 
+// Start vector for the two-site block (k+1, k+2) after a truncation at
+// (k, k+1) moving right.  With U_a the kept eigenvectors of cut sector a
+// (the new left-canonical tensor at site k), the kept part of psi is
+// C = U_a^T psi_(a,c) in the basis |a'> (x) |(sigma2 r) S_c>.  The right
+// block state r at bond k+2 is sum B(r; sigma3 r') |(sigma3 r') S_r> with B
+// the right-canonical tensor of site k+2, so in the next block's middle-cut
+// basis ((a' sigma2) S'', (sigma3 r') S_r) S the coefficients are
+//   sum_{S_c} <((a' sigma2) S'', r) S | (a', (sigma2 r) S_c) S> C B,
+// one 6j recoupling per block (no fermion sign: the order of the sites is
+// unchanged).  Without truncation it is the same state as psi.
+static void next_block_guess(dmrg_ctx* c, int k, const PsiLayout& lay, const double* psi,
+                      const std::vector<CutSector>& secs, const std::vector<std::vector<int>>& kept,
+                      const std::vector<int>& new_of, const std::vector<double>& hV, const Bond& nb) {
+  Context& C = *c->C;
+  const SiteTensor& B = C.sites[k + 2];
+  if (B.left || B.buf < 0) return;
+  int64_t nbv = 0;
+  for (auto& bk : B.blocks) nbv = std::max<int64_t>(nbv, bk.off + (int64_t)bk.rows * bk.cols);
+  std::vector<double> bv((size_t)std::max<int64_t>(nbv, 1));
+  if (nbv) c->ex->download(bv.data(), C.ptr(B.buf), (size_t)nbv * 8);
+  // C = U^T psi per old super-block whose left sector keeps states
+  std::map<std::pair<int, int>, int> sec_index;
+  for (size_t si = 0; si < secs.size(); ++si) sec_index[{secs[si].n, secs[si].s2}] = (int)si;
+  std::vector<std::vector<double>> Cm(lay.sbs.size());
+  for (size_t sbi = 0; sbi < lay.sbs.size(); ++sbi) {
+    const auto& sb = lay.sbs[sbi];
+    const int si = sec_index.at({sb.an, sb.as2});
+    if (new_of[si] < 0) continue;
+    const int da = (int)kept[si].size(), dim = secs[si].dim;
+    std::vector<double>& m = Cm[sbi];
+    m.assign((size_t)da * sb.ncols, 0.0);
+    for (int r = 0; r < sb.nrows; ++r) {
+      const double* prow = psi + sb.off + (int64_t)r * sb.ncols;
+      for (int q = 0; q < da; ++q) {
+        const double u = hV[(size_t)secs[si].off + (size_t)r * dim + kept[si][q]];
+        if (u == 0.0) continue;
+        double* mrow = m.data() + (size_t)q * sb.ncols;
+        for (int col = 0; col < sb.ncols; ++col) mrow[col] += u * prow[col];
+      }
+    }
+  }
+  const Bond& b2 = C.bonds[k + 2];
+  const Bond& b3 = C.bonds[k + 3];
+  PsiLayout nl;
+  nl.build(nb, b3, c->opts.n_elec, c->opts.two_s);
+  std::vector<double> g((size_t)nl.size, 0.0);
+  const int S = c->opts.two_s;
+  auto loc2s = [](int sig) { return sig == 1 ? 1 : 0; };
+  for (const auto& sb2 : nl.sbs) {
+    for (const auto& rr : sb2.rows) {
+      const Sector& ap = nb.secs[rr.il];  // a' (new bond k+1), site sigma2 = rr.s1
+      int si = -1;
+      for (size_t q = 0; q < secs.size(); ++q)
+        if (new_of[q] == rr.il) si = (int)q;
+      if (si < 0) continue;
+      for (const auto& cc : sb2.cols) {  // sigma3 = cc.s2, r' = bond k+3 sector cc.ir
+        for (size_t ir = 0; ir < b2.secs.size(); ++ir) {
+          const Sector& rs = b2.secs[ir];
+          if (rs.n != sb2.cn || rs.s2 != sb2.cs2) continue;  // r is (sigma3 r') coupled to S_r = S''_c
+          auto bit = B.find.find({(int)ir, cc.s2, cc.ir});
+          if (bit == B.find.end()) continue;
+          const auto& bk = B.blocks[bit->second];  // D_r x D_r'
+          for (size_t sbi = 0; sbi < lay.sbs.size(); ++sbi) {
+            const auto& sb = lay.sbs[sbi];
+            if (Cm[sbi].empty() || sb.an != ap.n || sb.as2 != ap.s2) continue;
+            int c0 = -1, dr = 0;
+            for (const auto& col : sb.cols)
+              if (col.s2 == rr.s1 && col.ir == (int)ir) {
+                c0 = col.c0;
+                dr = col.dr;
+              }
+            if (c0 < 0) continue;
+            // <((a' sigma2) S'', r) S | (a', (sigma2 r) S_c) S>
+            const int j1 = ap.s2, j2 = loc2s(rr.s1), j3 = rs.s2, J12 = sb2.as2, J23 = sb.cs2;
+            const int ph = (j1 + j2 + j3 + S) / 2;
+            const double w = ((ph & 1) ? -1.0 : 1.0) * std::sqrt((J12 + 1.0) * (J23 + 1.0)) *
+                             sixj2(j1, j2, J12, j3, S, J23);
+            if (w == 0.0) continue;
+            const int da = rr.dl;
+            for (int i = 0; i < da; ++i) {
+              const double* crow = Cm[sbi].data() + (size_t)i * sb.ncols + c0;
+              double* grow = g.data() + sb2.off + (int64_t)(rr.r0 + i) * sb2.ncols + cc.c0;
+              for (int t = 0; t < dr; ++t) {
+                const double ct = w * crow[t];
+                if (ct == 0.0) continue;
+                const double* brow = bv.data() + bk.off + (int64_t)t * bk.cols;
+                for (int j = 0; j < cc.dr; ++j) grow[j] += ct * brow[j];
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  c->guess.swap(g);
+  c->guess_k = k + 1;
+}
+
 extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int d_max, double eps_tr,
                              double* trunc_err, int* d_kept) {
   return dmrg_truncate_dbss(c, k, psi, dir, 0, d_max, eps_tr, trunc_err, d_kept);
@@ -594,6 +694,13 @@ extern "C" int dmrg_truncate_dbss(dmrg_ctx* c, int k, const double* psi, int dir
     T.buf = C.new_buf(std::max<int64_t>((int64_t)vals.size(), 1));
     if (!vals.empty()) ex->upload(C.ptr(T.buf), vals.data(), vals.size() * 8);
     lap("select + site tensor");
+    // ---- start vector for the block (k+1, k+2) the sweep moves to
+    c->guess.clear();
+    c->guess_k = -1;
+    if (dir > 0 && c->opts.next_guess && k + 3 <= C.n) {
+      next_block_guess(c, k, lay, psi, secs, kept, new_of, hV, nb);
+      lap("next-block start vector");
+    }
     // ---- grow the operator block across the cut, move the two-site block if possible
     c->reset_plan();
     const bool keep = c->opts.keep_blocks != 0;
@@ -679,5 +786,14 @@ extern "C" int dmrg_get_site(dmrg_ctx* c, int j, double* values, long long* n) {
 extern "C" int dmrg_current_block(dmrg_ctx* c, int* k) {
   if (!c || !k) return dmrg_fail(DMRG_ERR_ARG, "dmrg_current_block: null argument");
   *k = c->C->k;
+  return DMRG_OK;
+}
+
+extern "C" int dmrg_next_guess(dmrg_ctx* c, int k, double* psi, long long n) {
+  if (!c || !psi) return dmrg_fail(DMRG_ERR_ARG, "dmrg_next_guess: null argument");
+  if (c->guess_k < 0 || c->guess_k != k || c->C->k != k)
+    return dmrg_fail(DMRG_ERR_ARG, "dmrg_next_guess: no start vector carried to this block");
+  if (n != (long long)c->guess.size()) return dmrg_fail(DMRG_ERR_SHAPE, "dmrg_next_guess: wrong length");
+  std::copy(c->guess.begin(), c->guess.end(), psi);
   return DMRG_OK;
 }

@@ -29,6 +29,9 @@ struct dmrg_ctx {
   int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1, b_inp = -1;
   void* d_pidx = nullptr;  // padded psi index -> caller index (int32, -1 = padding)
   long long plan_serial = 0;  // bumped whenever a new H*psi plan is made
+  // start vector carried by the last truncation to the block it moved to
+  std::vector<double> guess;
+  int guess_k = -1;
   // When set, the Davidson's matvecs y = H x (device FP64 vectors of the
   // plan's length) go through this instead of hpsi_device: the batched
   // Davidson gathers them into one grouped launch for several contexts.
