@@ -28,14 +28,14 @@ PEAK = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}  # dense MFMA TFLOP/s, MI355X
 
 def workload(name):
     from synth.integrals import huckel_chain, iron_sulfur_like, small_cas
-    if name == "cfg0":
+    if name == "cas8_d64":
         h, g, _ = small_cas(8, 0)
         return dict(name="CAS(8,8) S=0 D=64 centre two-site block", n=8, N=8, two_s=0, D=64, k=3, h=h, g=g, seed=0)
-    if name == "cfg1":
+    if name == "cas32_d1024":
         h, g, _ = huckel_chain(32, 1, naux=96)
         return dict(name="CAS(32,32) S=0 D=1024 centre two-site block, Hueckel-chain integrals", n=32, N=32,
                     two_s=0, D=1024, k=15, h=h, g=g, seed=1)
-    if name == "cfg4":
+    if name == "cas82_d4096":
         h, g, _ = iron_sulfur_like(4)
         return dict(name="CAS(82,82) S=0 D=4096 centre two-site block, Fe-S-like integrals", n=82, N=82, two_s=0,
                     D=4096, k=40, h=h, g=g, seed=4)
@@ -67,7 +67,7 @@ def measured_traffic(config):
     """HBM bytes of the dominant kernel per BF16 H*psi, from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary of the CAS(82,82) workload,
     or None if there is none or the kernel source changed since."""
-    if config != "cfg4" or not os.path.exists(TRAFFIC_FILE):
+    if config != "cas82_d4096" or not os.path.exists(TRAFFIC_FILE):
         return None, None
     from paper_2503_20700_amd.rocprof_summary import source_sha256
     with open(TRAFFIC_FILE) as f:
@@ -148,7 +148,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default=os.environ.get("DMRG_BENCH_CONFIG", "cfg4"))
+    ap.add_argument("--config", default=os.environ.get("DMRG_BENCH_CONFIG", "cas82_d4096"),
+                    help="cas82_d4096 (default), cas32_d1024, cas8_d64, or batch48")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dmrg-step", action="store_true", help="skip the timed Davidson + truncation step")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the converged mixed-vs-FP64 case")

@@ -20,7 +20,7 @@ def _workload(name):
     return bench.workload(name)
 
 
-@pytest.mark.parametrize("name", ["cfg1", "cfg4"], ids=["cas32_d1024", "cas82_d4096"])
+@pytest.mark.parametrize("name", ["cas32_d1024", "cas82_d4096"], ids=["cas32_d1024", "cas82_d4096"])
 def test_fullsize_properties(name):
     from paper_2503_20700_amd.binding import BF16, DMRG, FP64
     from synth.mps import random_mps, random_psi

@@ -66,9 +66,9 @@ def test_bench_reports_traffic_only_for_the_kernel_source_it_was_taken_on():
     from paper_2503_20700_amd.rocprof_summary import source_sha256
     with open(bench.TRAFFIC_FILE) as f:
         t = json.load(f)
-    total, detail = bench.measured_traffic("cfg4")
+    total, detail = bench.measured_traffic("cas82_d4096")
     if t["source_sha256"] == source_sha256():
         assert total == t["hbm_bytes_per_hpsi"] and detail["launches"] == t["launches"]
     else:
         assert total is None and detail is None
-    assert bench.measured_traffic("cfg1") == (None, None)
+    assert bench.measured_traffic("cas32_d1024") == (None, None)
