@@ -92,11 +92,27 @@ typedef struct {
   int next_guess;              /* 1: dmrg_truncate moving right (+1) also forms the
                                   start vector of the block it moves to (read it
                                   with dmrg_next_guess)                            */
+  long long hbm_budget_bytes;  /* cap on the device memory the context's buffers
+                                  hold (operator blocks and their low-precision
+                                  copies, H*psi intermediates, Davidson vectors);
+                                  checked on the host before each allocation, which
+                                  fails with DMRG_ERR_BUDGET instead of exceeding it
+                                  (the executor's task lists and split-K partial
+                                  tiles come on top); 0: no cap                     */
 } dmrg_opts;
 
-/* Create a context; copies h (n*n) and g (n^4).  Errors: ARG, SYMMETRY
- * (N odd with 2S even, N > 2n, ...), NONFINITE. */
+/* Create a context; copies h (n*n) and g (n^4).  h must be symmetric and g
+ * 8-fold symmetric ((pq|rs) = (qp|rs) = (pq|sr) = (rs|pq), real orbitals),
+ * to 1e-12 of their largest element.  Errors: ARG (null, sizes, an integral
+ * without these symmetries, hbm_budget_bytes < 0), SYMMETRY (N odd with 2S
+ * even, N > 2n, ...), NONFINITE. */
 int dmrg_create(dmrg_ctx **out, const dmrg_opts *opts, const double *h, const double *g);
+
+/* Replace the context's options between calls (e.g. Davidson tolerances and
+ * precisions that change from sweep to sweep).  Only davidson_*, hpsi_prec,
+ * hpsi_graph and next_guess may differ from the current options; the other
+ * fields must be passed unchanged.  Errors: ARG. */
+int dmrg_update_opts(dmrg_ctx *c, const dmrg_opts *opts);
 
 /* Load a mixed-canonical MPS around the two-site block (k, k+1) and build the
  * left operator block at bond k and the right operator block at bond k+2 on
@@ -127,7 +143,9 @@ int dmrg_hpsi_dev(dmrg_ctx *c, int k, const void *d_in, void *d_out, int prec);
  * NULL = the null stream): the product starts after all work queued on
  * hip_stream before the call (which may still be producing d_in), and work
  * queued on hip_stream after the call runs after d_out is written.  Neither
- * side is host-synchronised for this ordering.  Errors as dmrg_hpsi_dev. */
+ * side is host-synchronised for this ordering: the call returns once the
+ * work is queued (the first call of a precision on a new block also prepares
+ * its task lists, which waits for the device).  Errors as dmrg_hpsi_dev. */
 int dmrg_hpsi_dev_stream(dmrg_ctx *c, int k, const void *d_in, void *d_out, int prec, void *hip_stream);
 
 /* Diagonal of H_eff at the current block (host, n_elems). */
@@ -154,7 +172,9 @@ int dmrg_davidson_step(dmrg_ctx *c, int k, double *psi_inout, double *energy, do
  * The kept eigenvectors form a new left-canonical tensor at site k (+1) or a
  * right-canonical tensor at site k+1 (-1), and the operator block is grown to
  * bond k+1 on the GPU.  If keep_blocks was set, the two-site block then moves
- * to (k+1, k+2) or (k-1, k).  trunc_err = discarded weight / total weight. */
+ * to (k+1, k+2) or (k-1, k).  trunc_err = discarded weight / total weight.
+ * Returns NOCONV (all outputs still written) if the batched eigensolver left
+ * a sector's density matrix unconverged to its rounding floor. */
 int dmrg_truncate(dmrg_ctx *c, int k, const double *psi, int direction, int d_max, double eps_tr,
                   double *trunc_err, int *d_kept);
 
@@ -193,9 +213,14 @@ int dmrg_current_block(dmrg_ctx *c, int *k);
  * with their sector spins 2S; returns the count in *n. */
 int dmrg_cut_spectrum(dmrg_ctx *c, double *values, int *two_s, int *n, int capacity);
 
-/* Counters: out[0] = flops of one H*psi, out[1] = bytes of operator blocks
- * (left + right, FP64), out[2] = peak device bytes, out[3] = number of terms,
- * out[4] = number of block-product tasks per H*psi. */
+/* Counters: out[0] = algorithmic flops of one H*psi (2mnk over the rows and
+ * columns of structurally non-zero block products), out[1] = bytes of operator
+ * blocks (left + right, FP64), out[2] = peak device bytes, out[3] = number of
+ * terms, out[4] = number of block-product tasks per H*psi, out[5] = flops the
+ * launches execute (row segments merged for fuller tiles include some zero
+ * rows), out[6] = 2mnk over every row and column of each intermediate a term
+ * touches (an upper bound that also counts structurally zero rows and unread
+ * columns).  n: number of entries wanted (at most 7). */
 int dmrg_stats(dmrg_ctx *c, double *out, int n);
 
 /* Device-event timing of the library's GEMM launches on its own stream.
@@ -249,6 +274,16 @@ void dmrg_batch_destroy(dmrg_batch *b);
  * dmrg_batch_hpsi), HIP, NOCONV, NONFINITE. */
 int dmrg_batch_davidson(dmrg_batch *b, double *const *psi, double *energy, double *resid, int *n_matvec_lowprec,
                         int *n_matvec_fp64, int *status);
+
+/* The SU(2) coupling coefficients the planner weights every term with (Sec.
+ * "Conservation of the total spin": the Clebsch-Gordan layer kept apart from
+ * the tensor layer), exposed for checking against independent tables.  All
+ * arguments are doubled spins 2j (and doubled projections 2m).  kind 0:
+ * <j1 m1; j2 m2 | J M> from two_j = (2j1, 2m1, 2j2, 2m2, 2J, 2M); kind 1: the
+ * 6j symbol {j1 j2 j3; j4 j5 j6} from six values; kind 2: the 9j symbol
+ * {j1 j2 j3; j4 j5 j6; j7 j8 j9} from nine values, row by row.  Host only.
+ * Errors: ARG (null pointer, bad kind, negative spin). */
+int dmrg_su2_coefficient(int kind, const int *two_j, double *value);
 
 const char *dmrg_last_error(void);
 void dmrg_destroy(dmrg_ctx *c);

@@ -14,7 +14,9 @@ Modules
   cg        exact Clebsch-Gordan coefficients (Racah's formula, rational arithmetic)
   fock      determinant space, the Hamiltonian and S^2 acting on it, FCI
   mps_fock  SU(2) MPS -> M-resolved Fock-space vectors, V and V^T
-  heff      H_eff psi by definition; dense H_eff for small cases
-  davidson  Davidson eigensolver (diagonal preconditioner, residual criterion)
-  truncate  reduced-density-matrix truncation of the two-site wavefunction
+  heff      H_eff psi by definition; dense H_eff for small cases (its lowest
+            eigenpair, from numpy's dense eigensolver, is the reference for
+            the library's Davidson)
+  truncate  Schmidt values of the two-site wavefunction, discarded weight,
+            SU(2) multiplet grouping and the dynamic block state selection rule
 """

@@ -34,7 +34,8 @@ class Opts(ct.Structure):
                 ("davidson_max_subspace", ct.c_int), ("hpsi_prec", ct.c_int),
                 ("work_budget_elems", ct.c_longlong), ("keep_blocks", ct.c_int),
                 ("davidson_refine_iter", ct.c_int), ("davidson_jd_inner", ct.c_int),
-                ("davidson_lowprec_iter", ct.c_int), ("hpsi_graph", ct.c_int), ("next_guess", ct.c_int)]
+                ("davidson_lowprec_iter", ct.c_int), ("hpsi_graph", ct.c_int), ("next_guess", ct.c_int),
+                ("hbm_budget_bytes", ct.c_longlong)]
 
 
 _LIBS = {}
@@ -72,6 +73,8 @@ def load(path=None):
         "dmrg_truncate_dbss": (I, [P, I, dp, I, I, I, D, dp, ip]),
         "dmrg_cut_spectrum": (I, [P, dp, ip, ip, I]),
         "dmrg_stats": (I, [P, dp, I]),
+        "dmrg_su2_coefficient": (I, [I, ip, dp]),
+        "dmrg_update_opts": (I, [P, ct.POINTER(Opts)]),
         "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
         "dmrg_kernel_timing": (I, [P, I, dp, llp]),
         "dmrg_current_block": (I, [P, ip]),
@@ -98,7 +101,21 @@ def exported_symbols():
             "dmrg_heff_diag",
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_truncate_dbss", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
             "dmrg_kernel_timing", "dmrg_current_block", "dmrg_next_guess", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
-            "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_batch_davidson", "dmrg_last_error", "dmrg_destroy"]
+            "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_batch_davidson", "dmrg_su2_coefficient", "dmrg_update_opts",
+            "dmrg_last_error",
+            "dmrg_destroy"]
+
+
+def su2_coefficient(kind, two_j, lib=None):
+    """The library's CG (kind 0), 6j (kind 1) or 9j (kind 2) coefficient for
+    doubled spins two_j (dmrg_su2_coefficient)."""
+    L = load(lib)
+    a = (ct.c_int * len(two_j))(*[int(x) for x in two_j])
+    v = ct.c_double()
+    rc = L.dmrg_su2_coefficient(int(kind), a, ct.byref(v))
+    if rc != 0:
+        raise DMRGError(rc, L.dmrg_last_error().decode())
+    return v.value
 
 
 def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ident_b=False, alpha=1.0, beta=0.0,
@@ -139,14 +156,15 @@ class DMRG:
     def __init__(self, h, g, n_elec, two_s, e_core=0.0, davidson_tol=1e-7, davidson_max_iter=60,
                  davidson_max_subspace=24, hpsi_prec=FP64, work_budget_elems=0, keep_blocks=False,
                  davidson_refine_iter=0, davidson_jd_inner=0, davidson_lowprec_iter=-1, hpsi_graph=False,
-                 next_guess=False, lib=None):
+                 next_guess=False, hbm_budget_bytes=0, lib=None):
         self.lib = load(lib)
         h = np.ascontiguousarray(h, dtype=np.float64)
         g = np.ascontiguousarray(g, dtype=np.float64)
         n = h.shape[0]
         self.opts = Opts(n, n_elec, two_s, e_core, davidson_tol, davidson_max_iter, davidson_max_subspace,
                          hpsi_prec, work_budget_elems, int(keep_blocks), davidson_refine_iter,
-                         davidson_jd_inner, davidson_lowprec_iter, int(hpsi_graph), int(next_guess))
+                         davidson_jd_inner, davidson_lowprec_iter, int(hpsi_graph), int(next_guess),
+                         int(hbm_budget_bytes))
         self._h = ct.c_void_p()
         self._batches = weakref.WeakSet()
         self._check(self.lib.dmrg_create(ct.byref(self._h), ct.byref(self.opts), _dp(h), _dp(g)))
@@ -156,6 +174,18 @@ class DMRG:
         if rc != 0:
             raise DMRGError(rc, self.lib.dmrg_last_error().decode())
         return rc
+
+    def update_opts(self, **kw):
+        """Change Davidson / precision / graph / next-guess options in place
+        (dmrg_update_opts); keyword names are the dmrg_opts fields."""
+        o = Opts()
+        ct.pointer(o)[0] = self.opts
+        for key, val in kw.items():
+            if key not in dict(Opts._fields_):
+                raise TypeError(f"unknown option {key}")
+            setattr(o, key, int(val) if isinstance(val, bool) else val)
+        self._check(self.lib.dmrg_update_opts(self._h, ct.byref(o)))
+        self.opts = o
 
     def close(self):
         for b in list(getattr(self, "_batches", ())):
@@ -267,10 +297,10 @@ class DMRG:
         return ms.value, n.value
 
     def stats(self):
-        out = np.zeros(5)
-        self._check(self.lib.dmrg_stats(self._h, _dp(out), 5))
+        out = np.zeros(7)
+        self._check(self.lib.dmrg_stats(self._h, _dp(out), 7))
         return dict(hpsi_flops=out[0], op_bytes=out[1], peak_bytes=out[2], n_terms=int(out[3]),
-                    n_tasks=int(out[4]))
+                    n_tasks=int(out[4]), hpsi_flops_executed=out[5], hpsi_flops_dense_regions=out[6])
 
 
 class HpsiBatch:

@@ -50,8 +50,31 @@ extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, 
     return fail(DMRG_ERR_ARG, "dmrg_create: negative Davidson budget");
   if (o->hpsi_graph < 0 || o->hpsi_graph > 1) return fail(DMRG_ERR_ARG, "dmrg_create: hpsi_graph must be 0 or 1");
   if (o->next_guess < 0 || o->next_guess > 1) return fail(DMRG_ERR_ARG, "dmrg_create: next_guess must be 0 or 1");
+  if (o->hbm_budget_bytes < 0) return fail(DMRG_ERR_ARG, "dmrg_create: negative hbm_budget_bytes");
   const size_t n2 = (size_t)n * n, n4 = n2 * n2;
   if (!finite_all(h, n2) || !finite_all(g, n4)) return fail(DMRG_ERR_NONFINITE, "dmrg_create: non-finite integral");
+  {
+    // the operator scheme pairs (pq|rs) with its index permutations: real
+    // orbitals, h symmetric and g 8-fold symmetric
+    double hm = 0.0, gm = 0.0;
+    for (size_t i = 0; i < n2; ++i) hm = std::max(hm, std::fabs(h[i]));
+    for (size_t i = 0; i < n4; ++i) gm = std::max(gm, std::fabs(g[i]));
+    const double th = 1e-12 * std::max(hm, 1e-300), tg = 1e-12 * std::max(gm, 1e-300);
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < p; ++q)
+        if (std::fabs(h[(size_t)p * n + q] - h[(size_t)q * n + p]) > th)
+          return fail(DMRG_ERR_ARG, "dmrg_create: h is not symmetric");
+    auto G = [&](int p, int q, int r, int t) { return g[(((size_t)p * n + q) * n + r) * n + t]; };
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q)
+        for (int r = 0; r < n; ++r)
+          for (int t = 0; t < n; ++t) {
+            const double v = G(p, q, r, t);
+            if (std::fabs(v - G(q, p, r, t)) > tg || std::fabs(v - G(p, q, t, r)) > tg ||
+                std::fabs(v - G(r, t, p, q)) > tg)
+              return fail(DMRG_ERR_ARG, "dmrg_create: g is not 8-fold symmetric ((pq|rs) = (qp|rs) = (pq|sr) = (rs|pq))");
+          }
+  }
   try {
     auto s = std::make_unique<dmrg_ctx>();
     s->opts = *o;
@@ -62,11 +85,31 @@ extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, 
     I.e_core = o->e_core;
     s->ex.reset(make_hip_executor());
     s->C = std::make_unique<Context>(s->ex.get(), I, o->n_elec, o->two_s);
+    s->C->budget_bytes = o->hbm_budget_bytes;
     *out = s.release();
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_create: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_create: ") + e.what());
   }
+}
+
+extern "C" int dmrg_update_opts(dmrg_ctx* c, const dmrg_opts* o) {
+  if (!c || !o) return fail(DMRG_ERR_ARG, "dmrg_update_opts: null argument");
+  const dmrg_opts& p = c->opts;
+  if (o->n_orb != p.n_orb || o->n_elec != p.n_elec || o->two_s != p.two_s ||
+      o->work_budget_elems != p.work_budget_elems || o->keep_blocks != p.keep_blocks ||
+      o->hbm_budget_bytes != p.hbm_budget_bytes || o->e_core != p.e_core)
+    return fail(DMRG_ERR_ARG, "dmrg_update_opts: only the Davidson, precision, graph and next-guess fields may change");
+  if (o->hpsi_prec < 0 || o->hpsi_prec > 2) return fail(DMRG_ERR_ARG, "dmrg_update_opts: bad hpsi_prec");
+  if (o->davidson_max_iter < 0 || o->davidson_refine_iter < 0 || o->davidson_max_subspace < 0 ||
+      o->davidson_jd_inner < 0 || o->davidson_lowprec_iter < -1 || !(o->davidson_tol >= 0.0))
+    return fail(DMRG_ERR_ARG, "dmrg_update_opts: negative Davidson budget or tolerance");
+  if (o->hpsi_graph < 0 || o->hpsi_graph > 1 || o->next_guess < 0 || o->next_guess > 1)
+    return fail(DMRG_ERR_ARG, "dmrg_update_opts: hpsi_graph and next_guess must be 0 or 1");
+  c->opts = *o;
+  return DMRG_OK;
 }
 
 extern "C" void dmrg_destroy(dmrg_ctx* c) { delete c; }
@@ -179,8 +222,8 @@ extern "C" int dmrg_set_mps(dmrg_ctx* c, int k, const int* bs, const int* counts
     C.Lblk = std::move(L);
     C.Rblk = std::move(R);
     return DMRG_OK;
-  } catch (const std::bad_alloc&) {
-    return fail(DMRG_ERR_BUDGET, "dmrg_set_mps: out of memory");
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_set_mps: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_set_mps: ") + e.what());
   }
@@ -191,6 +234,8 @@ extern "C" int dmrg_psi_layout(dmrg_ctx* c, int k, long long* nsb, long long* de
   if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_psi_layout: no MPS loaded at this k");
   try {
     c->ensure_plan();
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_psi_layout: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_psi_layout: ") + e.what());
   }
@@ -219,6 +264,8 @@ extern "C" int dmrg_hpsi(dmrg_ctx* c, int k, const double* in, double* out, int 
     c->C->ex->download(out, c->C->ptr(c->b_out), (size_t)n * 8);
     if (flops) *flops = c->plan->flops;
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_hpsi: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_hpsi: ") + e.what());
   }
@@ -235,6 +282,8 @@ extern "C" int dmrg_hpsi_dev(dmrg_ctx* c, int k, const void* din, void* dout, in
     c->hpsi_device(prec);
     c->C->ex->copy_d2d(dout, c->C->ptr(c->b_out), (size_t)n * 8);
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_hpsi_dev: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_hpsi_dev: ") + e.what());
   }
@@ -249,10 +298,12 @@ extern "C" int dmrg_hpsi_dev_stream(dmrg_ctx* c, int k, const void* din, void* d
     const int64_t n = c->plan->lay.size;
     c->ex->wait_for(hip_stream);  // d_in may still be written by the caller's queued work
     c->ex->copy_d2d(c->C->ptr(c->b_in), din, (size_t)n * 8);
-    c->hpsi_device(prec);
+    c->hpsi_device(prec, false);  // queued only: no host wait
     c->ex->copy_d2d(dout, c->C->ptr(c->b_out), (size_t)n * 8);
     c->ex->signal(hip_stream);  // the caller's later work on the stream sees d_out
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_hpsi_dev_stream: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_hpsi_dev_stream: ") + e.what());
   }
@@ -265,6 +316,8 @@ extern "C" int dmrg_heff_diag(dmrg_ctx* c, int k, double* diag) {
     c->ensure_plan();
     c->ex->download(diag, c->C->ptr(c->b_diag), (size_t)c->plan->lay.size * 8);
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_heff_diag: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_heff_diag: ") + e.what());
   }
@@ -282,6 +335,8 @@ extern "C" int dmrg_kernel_timing(dmrg_ctx* c, int mode, double* ms, long long* 
       if (mode == 0) c->ex->timing(false);
     }
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_kernel_timing: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("dmrg_kernel_timing: ") + e.what());
   }
@@ -346,21 +401,38 @@ extern "C" int dmrg_gemm_selftest(int m, int n, int k, const double* A, int ta, 
     for (void* p : {dA, dB, dC}) if (p) ex->release(p);
     if (c64 != dC) ex->release(c64);
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("gemm_selftest: ") + e.what());
   } catch (const std::exception& e) {
     return fail(DMRG_ERR_HIP, std::string("gemm_selftest: ") + e.what());
   }
 }
 
+extern "C" int dmrg_su2_coefficient(int kind, const int* two_j, double* value) {
+  if (!two_j || !value) return fail(DMRG_ERR_ARG, "dmrg_su2_coefficient: null argument");
+  for (int i = 0; i < (kind == 2 ? 9 : 6); ++i)
+    if (two_j[i] < 0 && !(kind == 0 && (i == 1 || i == 3 || i == 5)))
+      return fail(DMRG_ERR_ARG, "dmrg_su2_coefficient: negative spin");
+  if (kind == 0) *value = cg2(two_j[0], two_j[1], two_j[2], two_j[3], two_j[4], two_j[5]);
+  else if (kind == 1) *value = sixj2(two_j[0], two_j[1], two_j[2], two_j[3], two_j[4], two_j[5]);
+  else if (kind == 2)
+    *value = ninej2(two_j[0], two_j[1], two_j[2], two_j[3], two_j[4], two_j[5], two_j[6], two_j[7], two_j[8]);
+  else return fail(DMRG_ERR_ARG, "dmrg_su2_coefficient: kind must be 0 (CG), 1 (6j) or 2 (9j)");
+  return DMRG_OK;
+}
+
 extern "C" int dmrg_stats(dmrg_ctx* c, double* out, int n) {
   if (!c || !out) return fail(DMRG_ERR_ARG, "dmrg_stats: null argument");
-  double v[5] = {0, 0, 0, 0, 0};
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
   if (c->plan) {
     v[0] = c->plan->flops;
     v[3] = (double)c->plan->terms.size();
     v[4] = (double)c->plan->n_stage_terms;
+    v[5] = c->plan->flops_exec;
+    v[6] = c->plan->flops_dense;
   }
   if (c->C->Lblk) v[1] = (double)(c->C->Lblk->bytes_f64() + c->C->Rblk->bytes_f64());
   v[2] = (double)c->C->peak_bytes;
-  for (int i = 0; i < n && i < 5; ++i) out[i] = v[i];
+  for (int i = 0; i < n && i < 7; ++i) out[i] = v[i];
   return DMRG_OK;
 }

@@ -100,9 +100,7 @@ void run_merged(dmrg_batch* b, int prec, const std::vector<const void*>& in, con
     const int64_t n = x->plan->lay.size;
     Context& C = *x->C;
     ex->copy_d2d(C.ptr(x->b_in), in[i], (size_t)n * 8);
-    ex->pack(C.ptr(x->b_inp, od), od, (const double*)C.ptr(x->b_in), (const int*)x->d_pidx,
-             (size_t)x->plan->lay.psize);
-    ex->zero(C.ptr(x->b_out, outd), (size_t)n * dtype_size(outd));
+    x->begin_hpsi(ex, prec);
   }
   for (size_t c = 0; c < M.stageL.size(); ++c) {
     ex->run(M.stageL[c]);
@@ -113,7 +111,7 @@ void run_merged(dmrg_batch* b, int prec, const std::vector<const void*>& in, con
     dmrg_ctx* x = b->ctx[i];
     const int64_t n = x->plan->lay.size;
     Context& C = *x->C;
-    if (outd != DT_F64) ex->convert(C.ptr(x->b_out), DT_F64, C.ptr(x->b_out, outd), outd, (size_t)n);
+    x->end_hpsi(ex, prec);
     ex->copy_d2d(out[i], C.ptr(x->b_out), (size_t)n * 8);
   }
   ex->sync();
@@ -245,6 +243,8 @@ extern "C" int dmrg_batch_hpsi(dmrg_batch* b, const void* const* d_in, void* con
     run_merged(b, b->prec, std::vector<const void*>(d_in, d_in + b->ctx.size()),
                std::vector<void*>(d_out, d_out + b->ctx.size()));
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return dmrg_fail(DMRG_ERR_BUDGET, std::string("dmrg_batch_hpsi: ") + e.what());
   } catch (const std::exception& e) {
     return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_batch_hpsi: ") + e.what());
   }
@@ -263,6 +263,8 @@ extern "C" int dmrg_batch_davidson(dmrg_batch* b, double* const* psi, double* en
       merged_for(b, x->opts.hpsi_prec);
       merged_for(b, DMRG_FP64);
     }
+  } catch (const std::bad_alloc& e) {
+    return dmrg_fail(DMRG_ERR_BUDGET, std::string("dmrg_batch_davidson: ") + e.what());
   } catch (const std::exception& e) {
     return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_batch_davidson: ") + e.what());
   }

@@ -91,7 +91,27 @@ struct Workspace {
 
 constexpr int kKeep = 4;  // Ritz vectors kept at a restart
 
+constexpr int kStall = 6;  // low-precision phase: iterations over which the residual must fall
+
 double* P(dmrg_ctx* c, int b) { return (double*)c->C->ptr(b); }
+
+// Ritz vectors carried from the low-precision phase into the FP64 phase
+// (DMRG_REFINE_KEEP overrides; 1 carries only the Ritz vector).
+int refine_keep(dmrg_ctx* c) {
+  (void)c;
+  if (const char* e = std::getenv("DMRG_REFINE_KEEP")) return std::max(1, std::min(kKeep, std::atoi(e)));
+  return kKeep;
+}
+
+// Scale of the spectrum for the rounding-level stop of the low-precision
+// phase: the largest |diagonal element| of H_eff (host copy of the diagonal).
+double diag_scale(dmrg_ctx* c, int64_t n) {
+  std::vector<double> d((size_t)n);
+  c->ex->download(d.data(), c->C->ptr(c->b_diag), (size_t)n * 8);
+  double m = 0.0;
+  for (double v : d) m = std::max(m, std::fabs(v));
+  return m;
+}
 
 // y = H x for device FP64 vectors via the plan buffers.
 void matvec(dmrg_ctx* c, const double* x, double* y, int prec, int64_t n) {
@@ -109,6 +129,8 @@ struct PhaseResult {
   int matvecs = 0;       // matvecs in the phase's own precision
   int inner_matvecs = 0;  // low-precision matvecs of the correction solves
   bool converged = false;
+  bool stalled = false;   // stopped because the residual no longer fell
+  int ritz_kept = 0;      // Ritz vectors left in the spare rows of V (lowest first)
 };
 
 double dot(Executor* ex, const double* a, const double* b, int64_t n) {
@@ -158,9 +180,18 @@ int jd_correction(dmrg_ctx* c, const Workspace& ws, int lo_prec, double theta, i
   return used;
 }
 
-// Davidson on the device basis V (rows), W = H V; starts from x (normalised).
+// Davidson on the device basis V (rows), W = H V.  Starts from x (normalised),
+// or with n_start > 1 from the orthonormal vectors in the spare rows
+// mmax..mmax+n_start-1 of V (lowest Ritz vector first).  stall > 0: stop
+// (stalled) when, over the last `stall` iterations, the residual has not
+// fallen below 0.7 of its earlier value and the Ritz value has moved down by
+// less than 1 % of the residual -- a low-precision operator stops improving
+// the Ritz pair at its rounding level, while from a poor start the residual
+// can stay flat as the Ritz value still falls.  keep_out > 0: on return the
+// keep_out lowest Ritz vectors of the final basis are left in the spare rows
+// of V.
 PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int max_iter, int jd_steps = 0,
-                           int jd_prec = DMRG_FP64) {
+                           int jd_prec = DMRG_FP64, int n_start = 1, int stall = 0, int keep_out = 0) {
   Executor* ex = c->ex.get();
   const int64_t n = ws.n;
   const int mmax = ws.mmax;
@@ -172,14 +203,39 @@ PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int
   double* t = P(c, ws.bt);
   const double* diag = (const double*)c->C->ptr(c->b_diag);
   PhaseResult res;
-  std::vector<double> G((size_t)mmax * mmax, 0.0), tmp(mmax), w, Y;
-  // V_0 = x, W_0 = H x
-  ex->copy_d2d(V, x, (size_t)n * 8);
-  matvec(c, V, W, prec, n);
-  res.matvecs++;
-  int m = 1;
-  ex->multidot(W, n, 1, V, n, tmp.data());
-  G[0] = tmp[0];
+  std::vector<double> G((size_t)mmax * mmax, 0.0), tmp(mmax), w, Y, hist, thist;
+  int m = 0;
+  if (n_start > 1) {
+    // V_0..V_{n_start-1} = the given vectors, W_i = H V_i in this phase's precision
+    n_start = std::min(n_start, std::min(kKeep, mmax - 1));
+    for (int q = 0; q < n_start; ++q) ex->copy_d2d(V + (int64_t)q * n, V + (int64_t)(mmax + q) * n, (size_t)n * 8);
+    for (int q = 0; q < n_start; ++q) {
+      matvec(c, V + (int64_t)q * n, W + (int64_t)q * n, prec, n);
+      res.matvecs++;
+    }
+    m = n_start;
+    for (int q = 0; q < m; ++q) {
+      ex->multidot(W, n, m, V + (int64_t)q * n, n, tmp.data());  // <W_j, V_q>
+      for (int j = 0; j < m; ++j) G[(size_t)q * mmax + j] = tmp[j];
+    }
+  } else {
+    // V_0 = x, W_0 = H x
+    ex->copy_d2d(V, x, (size_t)n * 8);
+    matvec(c, V, W, prec, n);
+    res.matvecs++;
+    m = 1;
+    ex->multidot(W, n, 1, V, n, tmp.data());
+    G[0] = tmp[0];
+  }
+  auto save_ritz = [&](int mm) {
+    const int kq = std::min(keep_out, mm);
+    for (int q = 0; q < kq; ++q) {
+      std::vector<double> yq(mm);
+      for (int i = 0; i < mm; ++i) yq[i] = Y[(size_t)i * mm + q];
+      ex->combine(V + (int64_t)(mmax + q) * n, V, n, mm, yq.data(), n, 0.0);
+    }
+    res.ritz_kept = kq;
+  };
   for (int it = 0; it < max_iter; ++it) {
     // Rayleigh-Ritz on span(V)
     std::vector<double> Gm((size_t)m * m);
@@ -198,11 +254,23 @@ PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int
     res.resid = std::sqrt(std::max(rr, 0.0));
     if (std::getenv("DMRG_VERBOSE"))
       std::fprintf(stderr, "[davidson] prec %d it %d m %d theta %.12f resid %.3e\n", prec, it, m, theta, res.resid);
+    hist.push_back(res.resid);
+    thist.push_back(theta);
     if (res.resid <= tol) {
       res.converged = true;
+      save_ritz(m);
       break;
     }
-    if (it == max_iter - 1) break;
+    if (stall > 0 && it >= stall && res.resid > 0.7 * hist[(size_t)(it - stall)] &&
+        thist[(size_t)(it - stall)] - theta < 1e-2 * res.resid) {
+      res.stalled = true;
+      save_ritz(m);
+      break;
+    }
+    if (it == max_iter - 1) {
+      save_ritz(m);
+      break;
+    }
     // thick restart: rotate the basis onto the `keep` lowest Ritz vectors,
     // built in the spare rows mmax..mmax+keep-1 and then moved to the front.
     if (m == mmax) {
@@ -325,18 +393,23 @@ int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* 
     int lo = 0, hi = 0;
     PhaseResult pr;
     const int lo_iter = c->opts.davidson_lowprec_iter < 0 ? max_iter : c->opts.davidson_lowprec_iter;
+    int carried = 1;
     if (prec != DMRG_FP64 && lo_iter > 0) {
-      // phase 1: low-precision matvecs down to the precision's noise floor
-      const double floor_tol = (prec == DMRG_BF16) ? 3e-3 : 1e-5;
-      pr = davidson_phase(c, ws, prec, std::max(tol, floor_tol), lo_iter);
+      // phase 1: low-precision matvecs until the residual reaches the
+      // precision's rounding level (relative to the Ritz value) or stalls
+      const double floor_rel = (prec == DMRG_BF16) ? 5e-5 : 1e-7;
+      const double floor_tol = floor_rel * std::max(1.0, std::fabs(diag_scale(c, n)));
+      pr = davidson_phase(c, ws, prec, std::max(tol, floor_tol), lo_iter, 0, DMRG_FP64, 1, kStall, refine_keep(c));
       lo = pr.matvecs;
+      carried = std::max(1, pr.ritz_kept);
     }
-    // phase 2 (or the whole solve for FP64): FP64 matvecs to tol, with
-    // Jacobi-Davidson corrections from low-precision inner solves if asked
+    // phase 2 (or the whole solve for FP64): FP64 matvecs to tol, starting
+    // from phase 1's lowest Ritz vectors, with Jacobi-Davidson corrections
+    // from low-precision inner solves if asked
     const int refine_iter =
         (prec != DMRG_FP64 && c->opts.davidson_refine_iter > 0) ? c->opts.davidson_refine_iter : max_iter;
     const int jd = prec != DMRG_FP64 ? c->opts.davidson_jd_inner : 0;
-    pr = davidson_phase(c, ws, DMRG_FP64, tol, refine_iter, jd, prec);
+    pr = davidson_phase(c, ws, DMRG_FP64, tol, refine_iter, jd, prec, carried);
     hi = pr.matvecs;
     lo += pr.inner_matvecs;
     c->ex->download(psi, c->C->ptr(ws.bx), (size_t)n * 8);
@@ -346,6 +419,8 @@ int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* 
     if (nhi) *nhi = hi;
     if (!pr.converged) return dmrg_fail(DMRG_ERR_NOCONV, "dmrg_davidson_step: residual above tolerance");
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return dmrg_fail(DMRG_ERR_BUDGET, std::string("dmrg_davidson_step: ") + e.what());
   } catch (const std::exception& e) {
     return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_davidson_step: ") + e.what());
   }
@@ -550,7 +625,8 @@ extern "C" int dmrg_truncate_dbss(dmrg_ctx* c, int k, const double* psi, int dir
     c->bind();
     C.run_batch(gb);
     lap("rho");
-    ex->sym_eig((double*)C.ptr(bR), (double*)C.ptr(bV), offs, sizes, 40, 1e-15);
+    double eig_worst = 0.0;
+    const int eig_left = ex->sym_eig((double*)C.ptr(bR), (double*)C.ptr(bV), offs, sizes, 40, 1e-15, &eig_worst);
     lap("eigensolve");
     std::vector<double> hR((size_t)tot), hV((size_t)tot);
     ex->download(hR.data(), C.ptr(bR), (size_t)tot * 8);
@@ -736,7 +812,13 @@ extern "C" int dmrg_truncate_dbss(dmrg_ctx* c, int k, const double* psi, int dir
       }
     }
     lap("block growth");
+    if (eig_left > 0)
+      return dmrg_fail(DMRG_ERR_NOCONV, "dmrg_truncate: density-matrix eigensolver left " + std::to_string(eig_left) +
+                                            " sector(s) unconverged after 40 sweeps (worst off-diagonal/norm " +
+                                            std::to_string(eig_worst) + "); outputs written");
     return DMRG_OK;
+  } catch (const std::bad_alloc& e) {
+    return dmrg_fail(DMRG_ERR_BUDGET, std::string("dmrg_truncate: ") + e.what());
   } catch (const std::exception& e) {
     return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_truncate: ") + e.what());
   }
@@ -777,6 +859,8 @@ extern "C" int dmrg_get_site(dmrg_ctx* c, int j, double* values, long long* n) {
   *n = cnt;
   try {
     if (values && cnt) c->ex->download(values, c->C->ptr(T.buf), (size_t)cnt * 8);
+  } catch (const std::bad_alloc& e) {
+    return dmrg_fail(DMRG_ERR_BUDGET, std::string("dmrg_get_site: ") + e.what());
   } catch (const std::exception& e) {
     return dmrg_fail(DMRG_ERR_HIP, std::string("dmrg_get_site: ") + e.what());
   }

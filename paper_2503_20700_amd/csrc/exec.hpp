@@ -101,10 +101,14 @@ class Executor {
   // Batched symmetric eigensolver (FP64): matrix i is sizes[i] x sizes[i],
   // row-major at A + offs[i]; on return its diagonal holds the eigenvalues
   // (unordered) and V + offs[i] the eigenvectors as columns.  Two-sided Jacobi
-  // with parallel (round-robin) ordering, one work-group per matrix; stops
-  // when the off-diagonal Frobenius norm falls below tol * ||A||_F.
-  virtual void sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes,
-                       int max_sweeps, double tol) = 0;
+  // with parallel (round-robin) ordering; a matrix is done when its
+  // off-diagonal Frobenius norm falls below max(tol, 4 n eps) * ||A||_F
+  // (n its size, eps the FP64 unit roundoff: the rounding floor of the
+  // rotations grows with n).  Returns the number of matrices still above
+  // their threshold after max_sweeps sweeps; *worst (nullable) receives the
+  // largest off-norm / ||A||_F among them (0 if none).
+  virtual int sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes,
+                      int max_sweeps, double tol, double* worst) = 0;
   // Per-launch timing of run() with device events on the executor's stream.
   // kernel_time() synchronises and returns (total ms, launches) since the
   // last call to timing(true).
@@ -114,6 +118,8 @@ class Executor {
   virtual std::string host_profile() const { return std::string(); }
   // dst[i] = idx[i] >= 0 ? src[idx[i]] : 0 for i < n, converted to dt_dst
   virtual void pack(void* dst, int dt_dst, const double* src, const int* idx, size_t n) = 0;
+  // dst[i] = src[idx[i]] (src of dtype dt_src) for i < n, in FP64
+  virtual void gather(double* dst, const void* src, int dt_src, const int* idx, size_t n) = 0;
   // element-wise precision conversion of n values
   virtual void convert(void* dst, int dt_dst, const void* src, int dt_src, size_t n) = 0;
   // ---- optional: record the calls made between capture_begin and

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <limits>
 #include <map>
 #include <unordered_map>
 #include <cstdio>
@@ -1157,6 +1158,13 @@ __global__ void fill_zero_kernel(unsigned char* p, long long nbytes) {
   if (t < nbytes && blockIdx.x == 0 && threadIdx.x < 16) p[t] = 0;
 }
 
+template <int DS>
+__global__ void gather_kernel(double* __restrict__ dst, const void* __restrict__ src, const int* __restrict__ idx,
+                              long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = ldv<DS>(src, idx[i]);
+}
+
 template <int DS, int DD>
 __global__ void convert_kernel(void* dst, const void* src, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -1899,6 +1907,15 @@ class HipExec : public Executor {
     else throw std::runtime_error("executor: unsupported pack dtype");
     HIP_OK(hipGetLastError());
   }
+  void gather(double* dst, const void* src, int ds, const int* idx, size_t n) override {
+    if (!n) return;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    if (ds == DT_F64) hipLaunchKernelGGL((gather_kernel<DT_F64>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
+    else if (ds == DT_F32) hipLaunchKernelGGL((gather_kernel<DT_F32>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
+    else if (ds == DT_BF16) hipLaunchKernelGGL((gather_kernel<DT_BF16>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
+    else throw std::runtime_error("executor: unsupported gather dtype");
+    HIP_OK(hipGetLastError());
+  }
   void convert(void* dst, int dd, const void* src, int ds, size_t n) override {
     if (!n) return;
     const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
@@ -1938,9 +1955,14 @@ class HipExec : public Executor {
     hipLaunchKernelGGL(precond_kernel, dim3(grid1(n)), dim3(256), 0, stream_, t, r, d, theta, eps, (long long)n);
     HIP_OK(hipGetLastError());
   }
-  void sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes, int max_sweeps,
-               double tol) override {
-    if (offs.empty()) return;
+  int sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes, int max_sweeps,
+              double tol, double* worst) override {
+    if (worst) *worst = 0.0;
+    if (offs.empty()) return 0;
+    auto thr2 = [&](int i) {
+      const double t = std::max(tol, 4.0 * sizes[i] * std::numeric_limits<double>::epsilon());
+      return t * t;
+    };
     const int nall = (int)offs.size();
     // per-matrix descriptors of a list of matrices (bases for the work indices)
     auto describe = [&](const std::vector<int>& ids, std::vector<JacMat>& M, long long& npair, long long& nblk,
@@ -1986,7 +2008,7 @@ class HipExec : public Executor {
     std::vector<int> active;
     for (int i = 0; i < nall; ++i) {
       fro2[i] = nrm[2 * i + 1];
-      if (sizes[i] > 1 && nrm[2 * i] > tol * tol * fro2[i]) active.push_back(i);
+      if (sizes[i] > 1 && nrm[2 * i] > thr2(i) * fro2[i]) active.push_back(i);
     }
     for (int sweep = 0; sweep < max_sweeps && !active.empty(); ++sweep) {
       describe(active, M, npair, nblk, nvrow, maxnp);
@@ -2004,9 +2026,14 @@ class HipExec : public Executor {
       HIP_OK(hipGetLastError());
       download(nrm.data(), dnorm, 2 * (size_t)nm * sizeof(double));
       std::vector<int> still;
+      std::vector<double> ratio;
       for (int j = 0; j < nm; ++j)
-        if (nrm[2 * j] > tol * tol * fro2[active[j]]) still.push_back(active[j]);
+        if (nrm[2 * j] > thr2(active[j]) * fro2[active[j]]) {
+          still.push_back(active[j]);
+          ratio.push_back(std::sqrt(nrm[2 * j] / std::max(fro2[active[j]], 1e-300)));
+        }
       active.swap(still);
+      if (worst) *worst = ratio.empty() ? 0.0 : *std::max_element(ratio.begin(), ratio.end());
     }
     release(dM);
     release(dnorm);
@@ -2014,6 +2041,7 @@ class HipExec : public Executor {
     release(dsn);
     release(dpp);
     release(dqq);
+    return (int)active.size();
   }
   hipStream_t stream() const { return stream_; }
 

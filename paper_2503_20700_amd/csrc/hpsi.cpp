@@ -129,28 +129,188 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
   const int S2 = two_s;
 
   // ---- per chunk task generation
+  //
+  // An X region is X_t = (L (x) s1) psi for one (term, direction, output
+  // super-block, input super-block); its rows are the row bands (l', s1') of
+  // the output super-block in internal order, its columns the padded columns
+  // of the input super-block.  A band no stage-L product writes is zero, and
+  // a column sub-block no stage-R product reads is not needed; both are left
+  // out of the launches and of the flop count.  Stage-R jobs (one per output
+  // super-block and column sub-block) are cut into row segments so that each
+  // product covers only the bands where its X is non-zero; adjacent segments
+  // are merged where fewer, fuller tiles cost less, and a zero band a merged
+  // segment reads is then written as zeros by stage L.
+  struct XBand {
+    std::vector<GemmTerm> prods;  // stage-L products; B offsets at column 0 of the input
+    bool zero_read = false;       // no product, but read inside a merged stage-R segment
+  };
+  struct XRegion {
+    int xo = 0, xi = 0;
+    int64_t base = 0;
+    std::vector<XBand> bands;   // per row sub-block of lay.sbs[xo]
+    std::vector<char> colread;  // per column sub-block of lay.sbs[xi]
+  };
+  struct RProd {
+    GemmTerm gt;  // A offset at row 0 of the region
+    int reg = 0;
+    bool dense = false;  // not an identity product (counts flops)
+  };
+  std::vector<XRegion> regs;
+  std::map<std::tuple<int, int, int, int>, int> xreg;  // (term, dir, out-left sb, in sb) -> region, -1 if zero
+  std::map<std::pair<int, int>, std::vector<RProd>> rjobs;  // (out sb, col idx) -> products
+  int64_t xoff = 0;
+  constexpr int kSegRows = 64;    // row tile of the stage-R launches (cost model of the segment merge)
+  constexpr double kSegK = 32.0;  // per-tile overhead, in K elements
+
   auto new_chunk = [&]() { plan->chunks.emplace_back(); };
   new_chunk();
-  // stage R jobs of the current chunk: (out sb, col idx) -> terms
-  std::map<std::pair<int, int>, std::vector<GemmTerm>> rjobs;
-  std::map<std::tuple<int, int, int, int>, std::pair<int64_t, bool>> xreg;  // (term, dir, out-left sb, in sb)
-  int64_t xoff = 0;
 
   auto flush_chunk = [&]() {
     HpsiPlan::Chunk& ch = plan->chunks.back();
+    // stage R: row segments per output (super-block, column sub-block)
     for (auto& [key, vec] : rjobs) {
       const auto& sb = lay.sbs[key.first];
       const auto& col = sb.cols[key.second];
-      GemmJob j;
-      j.C = BufRef{-2, sb.off + col.c0};  // -2: psi_out placeholder
-      j.m = sb.nrows;
-      j.n = col.dr;
-      j.ldc = sb.ncols;
-      j.accumulate = 1;
-      j.tbeg = (int64_t)ch.stageR.terms.size();
-      ch.stageR.terms.insert(ch.stageR.terms.end(), vec.begin(), vec.end());
-      j.tend = (int64_t)ch.stageR.terms.size();
-      ch.stageR.jobs.push_back(j);
+      const int nb = (int)sb.rows.size();
+      std::vector<int> ord(nb);
+      for (int i = 0; i < nb; ++i) ord[i] = i;
+      std::sort(ord.begin(), ord.end(), [&](int x, int y) { return sb.rows[x].ir0 < sb.rows[y].ir0; });
+      // membership is per X region: every product of a region has its zero bands
+      std::vector<int> rlist;
+      std::map<int, int> rpos;
+      std::vector<double> rk;
+      for (const RProd& rp : vec) {
+        auto ins = rpos.emplace(rp.reg, (int)rlist.size());
+        if (ins.second) {
+          rlist.push_back(rp.reg);
+          rk.push_back(0.0);
+        }
+        rk[ins.first->second] += rp.gt.k;
+      }
+      const size_t nr = rlist.size(), nw = (nr + 63) / 64;
+      struct Seg {
+        int p0, p1;  // positions in ord
+        int rows;
+        std::vector<uint64_t> mem;  // member regions
+        double kmem;                // summed K of the members' products
+      };
+      std::vector<Seg> segs;
+      std::vector<uint64_t> mem(nw);
+      for (int q = 0; q < nb; ++q) {
+        const int bi = ord[q];
+        std::fill(mem.begin(), mem.end(), 0);
+        double km = 0.0;
+        bool anyp = false;
+        for (size_t r = 0; r < nr; ++r)
+          if (!regs[rlist[r]].bands[bi].prods.empty()) {
+            mem[r >> 6] |= (uint64_t)1 << (r & 63);
+            km += rk[r];
+            anyp = true;
+          }
+        if (!anyp) continue;  // every product is zero here: psi' stays zero
+        if (!segs.empty() && segs.back().p1 == q && segs.back().mem == mem) {
+          segs.back().p1 = q + 1;
+          segs.back().rows += sb.rows[bi].dl;
+        } else {
+          segs.push_back(Seg{q, q + 1, sb.rows[bi].dl, mem, km});
+        }
+      }
+      auto cost = [&](int rows, double km) { return (double)((rows + kSegRows - 1) / kSegRows) * (km + kSegK); };
+      for (size_t i = 0; i + 1 < segs.size();) {
+        Seg& A = segs[i];
+        Seg& B = segs[i + 1];
+        if (A.p1 != B.p0) {
+          ++i;
+          continue;
+        }
+        std::vector<uint64_t> u(nw);
+        double ku = 0.0;
+        for (size_t w = 0; w < nw; ++w) u[w] = A.mem[w] | B.mem[w];
+        for (size_t r = 0; r < nr; ++r)
+          if (u[r >> 6] >> (r & 63) & 1) ku += rk[r];
+        if (cost(A.rows + B.rows, ku) <= cost(A.rows, A.kmem) + cost(B.rows, B.kmem)) {
+          A.p1 = B.p1;
+          A.rows += B.rows;
+          A.mem.swap(u);
+          A.kmem = ku;
+          segs.erase(segs.begin() + i + 1);
+        } else {
+          ++i;
+        }
+      }
+      for (const Seg& S : segs) {
+        const int row0 = sb.rows[ord[S.p0]].ir0;
+        GemmJob j;
+        j.C = BufRef{-7, sb.off + (int64_t)row0 * sb.ncols + col.c0};  // -7: psi_out in internal row order
+        j.m = S.rows;
+        j.n = col.dr;
+        j.ldc = sb.ncols;
+        j.accumulate = 1;
+        j.tbeg = (int64_t)ch.stageR.terms.size();
+        std::vector<int> nzrows(nr, 0);
+        for (size_t r = 0; r < nr; ++r) {
+          if (!(S.mem[r >> 6] >> (r & 63) & 1)) continue;
+          XRegion& R = regs[rlist[r]];
+          for (int q = S.p0; q < S.p1; ++q) {
+            XBand& bd = R.bands[ord[q]];
+            if (!bd.prods.empty()) nzrows[r] += sb.rows[ord[q]].dl;
+            else bd.zero_read = true;
+          }
+        }
+        for (const RProd& rp : vec) {
+          const int r = rpos[rp.reg];
+          if (!(S.mem[r >> 6] >> (r & 63) & 1)) continue;
+          GemmTerm gt = rp.gt;
+          gt.A.off += (int64_t)row0 * gt.lda;
+          ch.stageR.terms.push_back(gt);
+          if (rp.dense) {
+            ch.stageR.flops += 2.0 * nzrows[r] * col.dr * gt.k;
+            plan->flops_exec += 2.0 * S.rows * col.dr * gt.k;
+          }
+        }
+        j.tend = (int64_t)ch.stageR.terms.size();
+        ch.stageR.jobs.push_back(j);
+      }
+    }
+    // stage L: the bands stage R reads, over runs of the column sub-blocks it reads
+    for (const XRegion& R : regs) {
+      const auto& O = lay.sbs[R.xo];
+      const auto& In = lay.sbs[R.xi];
+      const int nc = (int)In.cols.size();
+      for (size_t bi = 0; bi < O.rows.size(); ++bi) {
+        const XBand& bd = R.bands[bi];
+        if (bd.prods.empty() && !bd.zero_read) continue;
+        const auto& ro = O.rows[bi];
+        for (int c0 = 0; c0 < nc;) {
+          if (!R.colread[c0]) {
+            ++c0;
+            continue;
+          }
+          int c1 = c0;
+          int width = 0;
+          while (c1 < nc && R.colread[c1]) width += In.cols[c1++].dr;
+          const int pc0 = In.cols[c0].pc0;
+          GemmJob j;
+          j.C = BufRef{-3, R.base + (int64_t)ro.ir0 * In.pncols + pc0};  // -3: X placeholder
+          j.m = ro.dl;
+          j.n = In.cols[c1 - 1].pc0 + In.cols[c1 - 1].dr - pc0;
+          j.ldc = In.pncols;
+          j.accumulate = 0;
+          j.tbeg = (int64_t)ch.stageL.terms.size();
+          for (const GemmTerm& g0 : bd.prods) {
+            GemmTerm gt = g0;
+            gt.B.off += pc0;
+            ch.stageL.terms.push_back(gt);
+            if (!(gt.flags & TF_IDENT_A)) {
+              ch.stageL.flops += 2.0 * ro.dl * width * gt.k;
+              plan->flops_exec += 2.0 * ro.dl * width * gt.k;
+            }
+          }
+          j.tend = (int64_t)ch.stageL.terms.size();
+          ch.stageL.jobs.push_back(j);
+          c0 = c1;
+        }
+      }
     }
     ch.xsize = xoff;
     plan->xmax = std::max(plan->xmax, xoff);
@@ -158,36 +318,31 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
     plan->n_stage_terms += ch.stageL.terms.size() + ch.stageR.terms.size();
     rjobs.clear();
     xreg.clear();
+    regs.clear();
     xoff = 0;
   };
 
   // Stage-L region: X(rows of left sector of `osb`) x (cols of input sb `isb`)
   // for term t in direction dir (0 forward: L[l'<-l] psi, 1 transposed).
-  auto get_x = [&](int ti, int dir, int osb, int isb) -> std::pair<int64_t, bool> {
+  auto get_x = [&](int ti, int dir, int osb, int isb) -> int {
     auto key = std::make_tuple(ti, dir, osb, isb);
     auto it = xreg.find(key);
     if (it != xreg.end()) return it->second;
     const Term4& t = terms[ti];
     const auto& O = lay.sbs[osb];  // provides output rows
     const auto& In = lay.sbs[isb];
-    HpsiPlan::Chunk& ch = plan->chunks.back();
-    const int64_t base = xoff;
     const Family* LF = t.L.is_id() ? nullptr : &L.family(t.L.fam);
     const SiteOp& so = sops[t.s1];
+    XRegion R;
+    R.xo = osb;
+    R.xi = isb;
+    R.bands.resize(O.rows.size());
+    R.colread.assign(In.cols.size(), 0);
     bool any = false;
-    std::vector<GemmJob> jobs;
-    for (const auto& ro : O.rows) {  // output row sub (l', s1') [dir 0]  /  (l, s1) [dir 1]
-      GemmJob j;
-      // X rows have the padded column layout of the input super-block
-      j.C = BufRef{-3, base + (int64_t)ro.r0 * In.pncols};  // -3: X placeholder
-      j.m = ro.dl;
-      j.n = In.pncols;
-      j.ldc = In.pncols;
-      j.accumulate = 0;
-      j.tbeg = (int64_t)ch.stageL.terms.size();
-      const Sector& so_sec = L.bond.secs[ro.il];
+    double dense_flops = 0.0;
+    for (size_t bi = 0; bi < O.rows.size(); ++bi) {  // output row sub (l', s1') [dir 0]  /  (l, s1) [dir 1]
+      const auto& ro = O.rows[bi];
       for (const auto& ri : In.rows) {
-        const Sector& si_sec = L.bond.secs[ri.il];
         // forward element is always <bra = (l' s1') of the term's output | ket = (l s1) of its input>
         int bl, kl, bs, ks, bsa, ksa;  // bra / ket sector idx, site idx, enlarged spins
         if (dir == 0) {
@@ -220,30 +375,27 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
         } else {
           gt.flags |= TF_IDENT_A;
         }
-        gt.B = BufRef{-6, In.poff + (int64_t)ri.r0 * In.pncols};  // -6: padded psi_in placeholder
+        gt.B = BufRef{-6, In.poff + (int64_t)ri.ir0 * In.pncols};  // -6: padded psi_in placeholder
         gt.ldb = In.pncols;
         // operator blocks, padded psi and X all have 8-element padded rows
         gt.flags |= TF_PAD_B | (LF ? TF_PAD_A : 0);
         gt.k = ri.dl;
         gt.alpha = w * r1;
-        ch.stageL.terms.push_back(gt);
-        if (LF) ch.stageL.flops += 2.0 * ro.dl * In.ncols * ri.dl;
+        R.bands[bi].prods.push_back(gt);
+        if (LF) dense_flops += 2.0 * ro.dl * In.ncols * ri.dl;
         any = true;
-        (void)so_sec;
-        (void)si_sec;
       }
-      j.tend = (int64_t)ch.stageL.terms.size();
-      jobs.push_back(j);
     }
-    std::pair<int64_t, bool> res{base, any};
-    if (any) {
-      for (auto& j : jobs) ch.stageL.jobs.push_back(j);
-      xoff += (int64_t)O.nrows * In.pncols;
-    } else {
-      ch.stageL.terms.resize(jobs.empty() ? ch.stageL.terms.size() : jobs.front().tbeg);
+    if (!any) {
+      xreg[key] = -1;
+      return -1;
     }
-    xreg[key] = res;
-    return res;
+    plan->flops_dense += dense_flops;
+    R.base = xoff;
+    xoff += (int64_t)O.nrows * In.pncols;
+    regs.push_back(std::move(R));
+    xreg[key] = (int)regs.size() - 1;
+    return (int)regs.size() - 1;
   };
 
   for (size_t ti = 0; ti < terms.size(); ++ti) {
@@ -271,15 +423,17 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
             // transposed: X over rows of In's left part, cols of O; output In
             const int xo = d ? (int)isb : osb;
             const int xi = d ? osb : (int)isb;
-            auto [xbase, any] = get_x((int)ti, d, xo, xi);
-            if (!any) continue;
+            const int rid = get_x((int)ti, d, xo, xi);
+            if (rid < 0) continue;
+            const int64_t xbase = regs[rid].base;
             const auto& Xrows = lay.sbs[xo];
             const auto& Xin = lay.sbs[xi];
             const auto& Out = d ? In : O;
             const int outsb = d ? (int)isb : osb;
             for (size_t oc = 0; oc < Out.cols.size(); ++oc) {
               const auto& co = Out.cols[oc];
-              for (const auto& ci : Xin.cols) {
+              for (size_t cidx = 0; cidx < Xin.cols.size(); ++cidx) {
+                const auto& ci = Xin.cols[cidx];
                 // forward element bra = (s2', r') of O, ket = (s2, r) of In
                 int bs, ks, br, kr;
                 if (d == 0) {
@@ -302,7 +456,10 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
                                                  t.kX2) *
                                   fsign(RF ? (std::abs(RF->dn) & 1) : 0, kLocN[ks]);
                 if (wR == 0.0) continue;
-                GemmTerm gt;
+                RProd rp;
+                rp.reg = rid;
+                rp.dense = RF != nullptr;
+                GemmTerm& gt = rp.gt;
                 gt.A = BufRef{-3, xbase + ci.pc0};
                 gt.lda = Xin.pncols;
                 gt.flags = TF_PAD_A;
@@ -316,8 +473,9 @@ std::unique_ptr<HpsiPlan> Context::plan_hpsi(int64_t x_budget) {
                 }
                 gt.k = ci.dr;
                 gt.alpha = t.c * wout * wR * r2;
-                rjobs[{outsb, (int)oc}].push_back(gt);
-                if (RF) plan->chunks.back().stageR.flops += 2.0 * Xrows.nrows * co.dr * ci.dr;
+                regs[rid].colread[cidx] = 1;
+                rjobs[{outsb, (int)oc}].push_back(rp);
+                if (RF) plan->flops_dense += 2.0 * Xrows.nrows * co.dr * ci.dr;
               }
             }
           }

@@ -94,10 +94,17 @@ Context::~Context() {
   for (size_t i = 0; i < bufs.size(); ++i) free_buf((int)i);
 }
 
+void Context::charge(int64_t bytes) {
+  if (budget_bytes > 0 && bytes_in_use + bytes > budget_bytes)
+    throw BudgetExceeded("device memory budget of " + std::to_string(budget_bytes) + " bytes exceeded (" +
+                         std::to_string(bytes_in_use) + " held, " + std::to_string(bytes) + " more requested)");
+}
+
 int Context::new_buf(int64_t nel) {
   DevBuf b;
   b.n = nel;
   if (nel > 0) {
+    charge(nel * 8);
     b.p[DT_F64] = ex->alloc((size_t)nel * 8);
     ex->zero(b.p[DT_F64], (size_t)nel * 8);
     bytes_in_use += nel * 8;
@@ -122,6 +129,7 @@ void Context::free_buf(int id) {
 void Context::ensure_dtype(int id, int dt) {
   DevBuf& b = bufs[id];
   if (dt == DT_F64 || b.p[dt] || b.n == 0) return;
+  charge(b.n * (int64_t)dtype_size(dt));
   b.p[dt] = ex->alloc((size_t)b.n * dtype_size(dt));
   bytes_in_use += b.n * (int64_t)dtype_size(dt);
   peak_bytes = std::max(peak_bytes, bytes_in_use);
@@ -131,6 +139,7 @@ void Context::ensure_dtype(int id, int dt) {
 void Context::alloc_dtype(int id, int dt) {
   DevBuf& b = bufs[id];
   if (b.p[dt] || b.n == 0) return;
+  charge(b.n * (int64_t)dtype_size(dt));
   b.p[dt] = ex->alloc((size_t)b.n * dtype_size(dt));
   bytes_in_use += b.n * (int64_t)dtype_size(dt);
   peak_bytes = std::max(peak_bytes, bytes_in_use);
@@ -1043,7 +1052,7 @@ void PsiLayout::build(const Bond& lb, const Bond& rb, int n_elec, int two_s) {
         for (int s1 = 0; s1 < 3; ++s1) {
           const Sector& s = lb.secs[il];
           if (s.n + kLocN[s1] == an && tri2(s.s2, kLocS2[s1], as2) && s.dim > 0) {
-            sb.rows.push_back(Row{(int)il, s1, sb.nrows, s.dim});
+            sb.rows.push_back(Row{(int)il, s1, sb.nrows, s.dim, 0});
             sb.nrows += s.dim;
           }
         }
@@ -1057,6 +1066,16 @@ void PsiLayout::build(const Bond& lb, const Bond& rb, int n_elec, int two_s) {
           }
         }
       if (sb.nrows == 0 || sb.ncols == 0) continue;
+      {
+        std::vector<int> ord(sb.rows.size());
+        for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sb.rows[x].s1 < sb.rows[y].s1; });
+        int r = 0;
+        for (int i : ord) {
+          sb.rows[i].ir0 = r;
+          r += sb.rows[i].dl;
+        }
+      }
       sb.off = size;
       size += (int64_t)sb.nrows * sb.ncols;
       sb.poff = psize;
@@ -1068,10 +1087,24 @@ void PsiLayout::build(const Bond& lb, const Bond& rb, int n_elec, int two_s) {
 std::vector<int> PsiLayout::pack_map() const {
   std::vector<int> m((size_t)psize, -1);
   for (const SB& sb : sbs)
-    for (int r = 0; r < sb.nrows; ++r)
-      for (const Col& c : sb.cols)
-        for (int q = 0; q < c.dr; ++q)
-          m[(size_t)(sb.poff + (int64_t)r * sb.pncols + c.pc0 + q)] = (int)(sb.off + (int64_t)r * sb.ncols + c.c0 + q);
+    for (const Row& rr : sb.rows)
+      for (int i = 0; i < rr.dl; ++i) {
+        const int64_t r = rr.r0 + i, ir = rr.ir0 + i;
+        for (const Col& c : sb.cols)
+          for (int q = 0; q < c.dr; ++q)
+            m[(size_t)(sb.poff + ir * sb.pncols + c.pc0 + q)] = (int)(sb.off + r * sb.ncols + c.c0 + q);
+      }
+  return m;
+}
+
+std::vector<int> PsiLayout::unpack_map() const {
+  std::vector<int> m((size_t)size, -1);
+  for (const SB& sb : sbs)
+    for (const Row& rr : sb.rows)
+      for (int i = 0; i < rr.dl; ++i) {
+        const int64_t r = rr.r0 + i, ir = rr.ir0 + i;
+        for (int c = 0; c < sb.ncols; ++c) m[(size_t)(sb.off + r * sb.ncols + c)] = (int)(sb.off + ir * sb.ncols + c);
+      }
   return m;
 }
 

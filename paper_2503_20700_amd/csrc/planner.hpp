@@ -25,6 +25,7 @@
 #pragma once
 #include <map>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -32,6 +33,13 @@
 #include "spin.hpp"
 
 namespace dmrg {
+
+// An allocation that would pass the context's device-memory budget.
+struct BudgetExceeded : std::bad_alloc {
+  std::string msg;
+  explicit BudgetExceeded(std::string m) : msg(std::move(m)) {}
+  const char* what() const noexcept override { return msg.c_str(); }
+};
 
 struct Sector {
   int n = 0, s2 = 0, dim = 0;
@@ -171,8 +179,11 @@ struct SiteTensor {
 // of 8 elements (pc0), rows have stride pncols (a multiple of 8) and
 // super-blocks start at 8-aligned offsets poff; padding holds zeros.
 struct PsiLayout {
+  // r0: first row in the caller's layout ((l, sigma1) order); ir0: first row
+  // in the internal order of the contraction buffers ((sigma1, l) order), in
+  // which the row bands a site operator cannot reach are contiguous.
   struct Row {
-    int il, s1, r0, dl;
+    int il, s1, r0, dl, ir0;
   };
   struct Col {
     int s2, ir, c0, dr, pc0;
@@ -185,8 +196,11 @@ struct PsiLayout {
   };
   std::vector<SB> sbs;
   int64_t size = 0, psize = 0;
-  // padded index -> caller index (-1 for padding)
+  // padded index (internal row order) -> caller index (-1 for padding)
   std::vector<int> pack_map() const;
+  // caller index -> index of the same element in an unpadded copy with rows
+  // in internal order (the layout stage R accumulates psi' in)
+  std::vector<int> unpack_map() const;
   void build(const Bond& lb, const Bond& rb, int n_elec, int two_s);
 };
 
@@ -202,7 +216,9 @@ struct HpsiPlan {
   };
   std::vector<Chunk> chunks;
   GemmBatch diag;   // diagonal of H_eff, accumulated into the diag buffer
-  double flops = 0.0;
+  double flops = 0.0;       // algorithmic: 2mnk over the rows and columns of structurally non-zero products
+  double flops_exec = 0.0;  // executed by the launches (merged row segments include some zero bands)
+  double flops_dense = 0.0; // 2mnk over whole X regions (every row band and column of a touched region)
   int64_t xmax = 0;
   size_t n_stage_terms = 0;
 };
@@ -264,6 +280,10 @@ class Context {
 
   double last_flops = 0.0;
   int64_t bytes_in_use = 0, peak_bytes = 0;
+  int64_t budget_bytes = 0;  // 0: no cap
+  // Account for `bytes` more device memory; throws BudgetExceeded (checked
+  // before the allocation is made) if that would pass budget_bytes.
+  void charge(int64_t bytes);
 };
 
 }  // namespace dmrg

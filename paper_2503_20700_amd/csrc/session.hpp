@@ -19,15 +19,18 @@ int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* 
 
 // psi_in, psi_out, X, ones, diag and padded-psi_in placeholders used by the
 // H*psi task lists
-enum { PH_IN = 1, PH_OUT = 2, PH_X = 3, PH_ONES = 4, PH_DIAG = 5, PH_INP = 6 };
+// (PH_OUTP: psi' accumulated with rows in the internal order, gathered into
+// PH_OUT at the end)
+enum { PH_IN = 1, PH_OUT = 2, PH_X = 3, PH_ONES = 4, PH_DIAG = 5, PH_INP = 6, PH_OUTP = 7 };
 
 struct dmrg_ctx {
   dmrg_opts opts{};
   std::unique_ptr<dmrg::Executor> ex;
   std::unique_ptr<dmrg::Context> C;
   std::unique_ptr<dmrg::HpsiPlan> plan;
-  int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1, b_inp = -1;
+  int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1, b_inp = -1, b_outp = -1;
   void* d_pidx = nullptr;  // padded psi index -> caller index (int32, -1 = padding)
+  void* d_uidx = nullptr;  // caller index -> index in b_outp (int32)
   long long plan_serial = 0;  // bumped whenever a new H*psi plan is made
   // start vector carried by the last truncation to the block it moved to
   std::vector<double> guess;
@@ -80,9 +83,11 @@ struct dmrg_ctx {
       work_bufs.clear();
       work_n = 0;
       work_mmax = 0;
-      for (int b : {b_in, b_out, b_x, b_ones, b_diag, b_inp}) C->free_buf(b);
+      for (int b : {b_in, b_out, b_x, b_ones, b_diag, b_inp, b_outp}) C->free_buf(b);
       if (d_pidx) ex->release(d_pidx);
       d_pidx = nullptr;
+      if (d_uidx) ex->release(d_uidx);
+      d_uidx = nullptr;
       if (C->Lblk) {
         for (auto& t : C->Lblk->tmp) C->free_buf(t.buf);
         C->Lblk->tmp.clear();
@@ -92,7 +97,7 @@ struct dmrg_ctx {
         C->Rblk->tmp.clear();
       }
     }
-    b_in = b_out = b_x = b_ones = b_diag = b_inp = -1;
+    b_in = b_out = b_x = b_ones = b_diag = b_inp = b_outp = -1;
     plan.reset();
   }
 
@@ -103,6 +108,7 @@ struct dmrg_ctx {
     C->ph[PH_ONES] = b_ones;
     C->ph[PH_DIAG] = b_diag;
     C->ph[PH_INP] = b_inp;
+    C->ph[PH_OUTP] = b_outp;
   }
 
   void ensure_plan() {
@@ -115,10 +121,14 @@ struct dmrg_ctx {
     b_x = C->new_buf(std::max<int64_t>(plan->xmax, 1));
     b_diag = C->new_buf(std::max<int64_t>(n, 1));
     b_inp = C->new_buf(std::max<int64_t>(plan->lay.psize, 1));
+    b_outp = C->new_buf(std::max<int64_t>(n, 1));
     {
       const std::vector<int> m = plan->lay.pack_map();
       d_pidx = ex->alloc(std::max<size_t>(m.size(), 1) * sizeof(int));
       if (!m.empty()) ex->upload(d_pidx, m.data(), m.size() * sizeof(int));
+      const std::vector<int> u = plan->lay.unpack_map();
+      d_uidx = ex->alloc(std::max<size_t>(u.size(), 1) * sizeof(int));
+      if (!u.empty()) ex->upload(d_uidx, u.data(), u.size() * sizeof(int));
     }
     int maxd = 1;
     for (auto& bd : C->bonds)
@@ -146,7 +156,7 @@ struct dmrg_ctx {
       C->alloc_dtype(b_in, od);
       C->alloc_dtype(b_inp, od);
       C->alloc_dtype(b_x, xd);
-      C->alloc_dtype(b_out, outd);
+      C->alloc_dtype(b_outp, outd);
     }
   }
 
@@ -167,25 +177,37 @@ struct dmrg_ctx {
     P.ready = true;
   }
 
+  // Before the stage launches (on executor e): the padded operand copy of
+  // b_in and a cleared accumulator b_outp.
+  void begin_hpsi(dmrg::Executor* e, int prec) {
+    const int od = op_dt(prec), outd = out_dt(prec);
+    e->pack(C->ptr(b_inp, od), od, (const double*)C->ptr(b_in), (const int*)d_pidx, (size_t)plan->lay.psize);
+    e->zero(C->ptr(b_outp, outd), (size_t)plan->lay.size * dmrg::dtype_size(outd));
+  }
+  // After them: b_out (FP64, caller layout) from b_outp.
+  void end_hpsi(dmrg::Executor* e, int prec) {
+    const int outd = out_dt(prec);
+    e->gather((double*)C->ptr(b_out), C->ptr(b_outp, outd), outd, (const int*)d_uidx, (size_t)plan->lay.size);
+  }
+
   // The launches of psi_out = H psi_in on b_in / b_out (prepared already).
   void enqueue_hpsi(int prec) {
-    const int64_t n = plan->lay.size;
-    const int od = op_dt(prec), outd = out_dt(prec);
-    ex->pack(C->ptr(b_inp, od), od, (const double*)C->ptr(b_in), (const int*)d_pidx, (size_t)plan->lay.psize);
-    ex->zero(C->ptr(b_out, outd), (size_t)n * dmrg::dtype_size(outd));
+    begin_hpsi(ex.get(), prec);
     Prepared& P = prep[prec];
     for (size_t i = 0; i < P.L.size(); ++i) {
       ex->run(P.L[i]);
       ex->run(P.R[i]);
     }
-    if (outd != dmrg::DT_F64) ex->convert(C->ptr(b_out), dmrg::DT_F64, C->ptr(b_out, outd), outd, (size_t)n);
+    end_hpsi(ex.get(), prec);
   }
 
   // psi_out = H psi_in on the device buffers b_in / b_out (FP64 masters).
   // With opts.hpsi_graph the launch sequence is recorded once per precision
   // and replayed (re-recorded when the executor's scratch moved), except
-  // while kernel timing is on.
-  void hpsi_device(int prec) {
+  // while kernel timing is on.  wait = false only queues the work on the
+  // executor's stream (the first call of a precision still prepares its task
+  // lists, which blocks the host).
+  void hpsi_device(int prec, bool wait = true) {
     prepare(prec);
     Prepared& P = prep[prec];
     if (opts.hpsi_graph && ex->graphs() && !ex->timing_on()) {
@@ -207,6 +229,6 @@ struct dmrg_ctx {
     } else {
       enqueue_hpsi(prec);
     }
-    ex->sync();
+    if (wait) ex->sync();
   }
 };

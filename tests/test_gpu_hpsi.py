@@ -222,6 +222,18 @@ def test_hpsi_dev_stream_orders_with_caller_stream():
         z = y * 1.0
     torch.cuda.synchronize()
     assert np.array_equal(z.cpu().numpy(), want)
+    # the call only queues its work: it returns while the caller's stream is
+    # still busy with the work queued before it (~30 ms of products here)
+    with torch.cuda.stream(s):
+        for _ in range(20):
+            a = (a @ a) * 1e-2
+        x.copy_(src)
+        dm.hpsi_dev(x.data_ptr(), y.data_ptr(), 0, stream=s.cuda_stream)
+        busy = not s.query()
+        z = y * 1.0
+    torch.cuda.synchronize()
+    assert busy
+    assert np.array_equal(z.cpu().numpy(), want)
 
 
 EDGE_CASES = [

@@ -208,3 +208,87 @@ def test_dbss_keep_worked_example():
     assert otr.dbss_keep(w, 0.0501, 9, 9) == 5    # capped by the count
     assert otr.dbss_keep(w, 0.0, 0, 4) == 4       # eps 0: fixed D
     assert otr.dbss_keep(w, 0.0, 0, 100) == 5
+
+
+# ---- exact identities at any size (tests/identities.py), pinned on the oracle ---------
+
+@pytest.mark.parametrize("n,ne,ts,d,k,seed", [(6, 6, 0, 16, 2, 2), (7, 7, 1, 16, 2, 3), (6, 6, 2, 16, 2, 4),
+                                              (8, 7, 1, 20, 3, 5)])
+def test_oracle_integral_shift_identities(n, ne, ts, d, k, seed):
+    import identities as ident
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    y = heff.hpsi(h, g, mps, lay, psi)
+    alpha, beta, gamma = 0.37, -0.21, 0.53
+    h2, g2 = ident.shift_integrals(h, g, alpha, beta)
+    hs, gs = ident.s2_integrals(n)
+    y2 = heff.hpsi(h2 + gamma * hs, g2 + gamma * gs, mps, lay, psi)
+    c = ident.shift_value(ne, ts, alpha, beta, gamma)
+    assert np.abs(y2 - y - c * psi).max() < 1e-10 * np.abs(y).max()
+    # a wrong S^2 factor, or a dropped beta term, would not pass
+    assert np.abs(y2 - y - (c + 0.01) * psi).max() > 1e-3
+
+
+def test_s2_integrals_reproduce_the_spin_operator():
+    import identities as ident
+    n = 3
+    hs, gs = ident.s2_integrals(n)
+    for n_up, n_dn in [(2, 1), (1, 1), (2, 2), (3, 1)]:
+        d = fock.sector_dets(n, n_up, n_dn)
+        hm = fock.hamiltonian_sparse(hs, gs, d).toarray()
+        s2, d0 = fock.s2_matrix(n, n_up + n_dn, n_up - n_dn)
+        assert np.array_equal(np.asarray(d0), np.asarray(d))
+        assert np.abs(hm - s2.toarray()).max() < 1e-12
+
+
+@pytest.mark.parametrize("flips", [(0,), (3,), (4,), (1, 3, 6), (2, 5, 7)])
+def test_oracle_sign_gauge_identity(flips):
+    import identities as ident
+    n, ne, ts, d, k, seed = 8, 8, 0, 20, 3, 9
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    y = heff.hpsi(h, g, mps, lay, psi)
+    h2, g2, mps2 = ident.transformed(h, g, mps, 0.0, 0.0, set(flips))
+    y2 = heff.hpsi(h2, g2, mps2, lay, ident.gauge_psi(psi, lay, k, set(flips)))
+    assert np.abs(ident.gauge_psi(y2, lay, k, set(flips)) - y).max() < 1e-10 * np.abs(y).max()
+    # the transformed integrals alone (old MPS) give a different operator
+    y3 = heff.hpsi(h2, g2, mps, lay, ident.gauge_psi(psi, lay, k, set(flips)))
+    if any(f not in (k, k + 1) for f in flips):
+        assert np.abs(ident.gauge_psi(y3, lay, k, set(flips)) - y).max() > 1e-6
+
+
+def test_rdm1_spin0_coupling_factor():
+    """[f+_p f_q]^0 built from Clebsch-Gordan coefficients on Fock space equals
+    -E_pq/sqrt(2) (Sec. "Conservation of the total spin", the coupled 1-RDM):
+    f+ = (a+_up, a+_dn) and f = (a_dn, -a_up) as rank-1/2 tensors."""
+    n = 3
+    a = fock.jw_annihilators(n)
+    ad = [x.T for x in a]
+    factor = GOLDEN["rdm1_coupled_factor"]["value"]
+    for p in range(n):
+        for q in range(n):
+            fdag = {1: ad[2 * p], -1: ad[2 * p + 1]}   # m = +1/2, -1/2 (twice m)
+            f = {1: a[2 * q + 1], -1: -a[2 * q]}
+            coupled = sum(cg(1, m, 1, -m, 0, 0) * fdag[m] @ f[-m] for m in (1, -1))
+            epq = ad[2 * p] @ a[2 * q] + ad[2 * p + 1] @ a[2 * q + 1]
+            assert np.abs(coupled - factor * epq).max() < 1e-14
+    assert abs(factor + 1.0 / math.sqrt(2.0)) < 1e-15
+
+
+def test_discarded_weight_is_the_truncation_residual():
+    """Eckart-Young: keeping the top-m Schmidt vectors leaves
+    |M - P_m M|_F^2 / |M|_F^2, computed here from the eigenvectors of M M^T."""
+    from oracle.truncate import discarded_weight
+    rng = np.random.default_rng(5)
+    m = rng.normal(size=(12, 9))
+    vals = np.linalg.svd(m, compute_uv=False)
+    w, u = np.linalg.eigh(m @ m.T)
+    u = u[:, np.argsort(-w)]
+    for keep in (0, 1, 4, 9):
+        pm = u[:, :keep] @ (u[:, :keep].T @ m)
+        ref = np.linalg.norm(m - pm) ** 2 / np.linalg.norm(m) ** 2
+        assert abs(discarded_weight(vals, keep) - ref) < 1e-12
+    # worked example: values 0.8 and 0.6 (in either order), keep one
+    assert abs(discarded_weight([0.6, 0.8], 1) - 0.36) < 1e-15
