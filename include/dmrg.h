@@ -275,6 +275,26 @@ void dmrg_batch_destroy(dmrg_batch *b);
 int dmrg_batch_davidson(dmrg_batch *b, double *const *psi, double *energy, double *resid, int *n_matvec_lowprec,
                         int *n_matvec_fp64, int *status);
 
+/* CAS-SCF orbital step (Sec. "Complete active space SCF": the orbitals are
+ * optimised at fixed RDMs between DMRG solves, through the rotated integrals
+ * h(kappa) and (pq|rs)(kappa)): the energy after the rotation kappa and its
+ * gradient, forward and backward on the GPU, all FP64.
+ *   orbitals: n = n_core + n_act + n_virt, ordered core, active, virtual;
+ *   h_full: n*n symmetric; B: naux*n*n, symmetric matrices B^L with
+ *     (pq|rs) = sum_L B^L_pq B^L_rs;
+ *   kappa: n*n, strict lower triangle read: K_pq = kappa_pq (p > q),
+ *     K_qp = -kappa_pq, U = exp(-K), h(kappa) = U^T h U, B^L(kappa) = U^T B^L U;
+ *   gamma: n_act^2 spin-summed 1-RDM gamma~_tu = <sum_s a+_ts a_us>;
+ *   Gamma: n_act^4, Gamma~_tuvw = <sum_st a+_ts a+_ut a_vt a_ws>;
+ *   energy: 2 sum_i h_ii + sum_ij [2(ii|jj) - (ij|ji)] + sum_tu F^c_tu gamma~_tu
+ *     + 1/2 sum_tuvw (tu|vw) Gamma~_tvwu, F^c_pq = h_pq + sum_i [2(pq|ii) - (pi|iq)],
+ *     integrals at kappa;
+ *   grad: n*n antisymmetric, grad[p*n+q] = dE/dkappa_pq for p > q.
+ * Host buffers, copied; nothing retained.  Errors: ARG (null, h or a B^L not
+ * symmetric), SHAPE (counts), NONFINITE, BUDGET, HIP. */
+int orb_grad(int n_core, int n_act, int n_virt, const double *h_full, const double *B, int naux,
+             const double *kappa, const double *gamma, const double *Gamma, double *energy, double *grad);
+
 /* The SU(2) coupling coefficients the planner weights every term with (Sec.
  * "Conservation of the total spin": the Clebsch-Gordan layer kept apart from
  * the tensor layer), exposed for checking against independent tables.  All

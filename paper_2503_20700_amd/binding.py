@@ -75,6 +75,7 @@ def load(path=None):
         "dmrg_stats": (I, [P, dp, I]),
         "dmrg_su2_coefficient": (I, [I, ip, dp]),
         "dmrg_update_opts": (I, [P, ct.POINTER(Opts)]),
+        "orb_grad": (I, [I, I, I, dp, dp, I, dp, dp, dp, dp, dp]),
         "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
         "dmrg_kernel_timing": (I, [P, I, dp, llp]),
         "dmrg_current_block": (I, [P, ip]),
@@ -102,6 +103,7 @@ def exported_symbols():
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_truncate_dbss", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
             "dmrg_kernel_timing", "dmrg_current_block", "dmrg_next_guess", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
             "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_batch_davidson", "dmrg_su2_coefficient", "dmrg_update_opts",
+            "orb_grad",
             "dmrg_last_error",
             "dmrg_destroy"]
 
@@ -116,6 +118,53 @@ def su2_coefficient(kind, two_j, lib=None):
     if rc != 0:
         raise DMRGError(rc, L.dmrg_last_error().decode())
     return v.value
+
+
+def orb_grad(n_core, n_act, n_virt, h, B, kappa, gamma, Gamma, lib=None):
+    """Energy at fixed active-space RDMs after the orbital rotation kappa, and
+    dE/dkappa (orb_grad): returns (energy, grad) with grad antisymmetric,
+    grad[p, q] = dE/dkappa_pq for p > q.  h: n x n, B: naux x n x n symmetric
+    density-fitting factors, kappa: n x n (strict lower triangle read),
+    gamma: n_act^2, Gamma: n_act^4 (Gamma~_tuvw = <a+_ts a+_ut a_vt a_ws>)."""
+    L = load(lib)
+    n = n_core + n_act + n_virt
+    h = np.ascontiguousarray(h, dtype=np.float64).reshape(n, n)
+    B = np.ascontiguousarray(B, dtype=np.float64).reshape(-1, n, n)
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64).reshape(n, n)
+    gamma = np.ascontiguousarray(gamma, dtype=np.float64).reshape(n_act, n_act)
+    Gamma = np.ascontiguousarray(Gamma, dtype=np.float64).reshape((n_act,) * 4)
+    e = np.zeros(1)
+    grad = np.zeros((n, n))
+    rc = L.orb_grad(n_core, n_act, n_virt, _dp(h), _dp(B), B.shape[0], _dp(kappa), _dp(gamma), _dp(Gamma), _dp(e),
+                    _dp(grad))
+    if rc != 0:
+        raise DMRGError(rc, L.dmrg_last_error().decode())
+    return float(e[0]), grad
+
+
+def orbital_energy_function():
+    """torch.autograd.Function E(kappa) at fixed integrals and RDMs: forward and
+    backward both run in the library (orb_grad: the gradient is the
+    hand-written backward on the GPU); backward scales it by the incoming
+    gradient.  Use: E = F.apply(kappa, n_core, n_act, n_virt, h, B, gamma, Gamma)
+    with kappa a float64 tensor (n x n, strict lower triangle read); the
+    gradient returned for kappa is dE/dkappa in its strict lower triangle."""
+    import torch
+
+    class OrbitalEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, kappa, n_core, n_act, n_virt, h, B, gamma, Gamma):
+            k = kappa.detach().to("cpu", torch.float64).numpy()
+            e, grad = orb_grad(n_core, n_act, n_virt, h, B, k, gamma, Gamma)
+            ctx.save_for_backward(torch.from_numpy(np.tril(grad, -1)).to(kappa.device, kappa.dtype))
+            return torch.tensor(e, dtype=kappa.dtype, device=kappa.device)
+
+        @staticmethod
+        def backward(ctx, g_out):
+            (grad,) = ctx.saved_tensors
+            return (g_out * grad, None, None, None, None, None, None, None)
+
+    return OrbitalEnergy
 
 
 def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ident_b=False, alpha=1.0, beta=0.0,

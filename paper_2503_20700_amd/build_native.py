@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT, "libdmrg_mi355x.so")
-HOST_SRC = ["su2.cpp", "spin.cpp", "planner.cpp", "hpsi.cpp", "api.cpp", "driver.cpp", "batch.cpp"]
+HOST_SRC = ["su2.cpp", "spin.cpp", "planner.cpp", "hpsi.cpp", "api.cpp", "driver.cpp", "batch.cpp", "orbital.cpp"]
 HIP_SRC = ["exec_hip.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

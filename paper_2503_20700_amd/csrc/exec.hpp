@@ -118,8 +118,12 @@ class Executor {
   virtual std::string host_profile() const { return std::string(); }
   // dst[i] = idx[i] >= 0 ? src[idx[i]] : 0 for i < n, converted to dt_dst
   virtual void pack(void* dst, int dt_dst, const double* src, const int* idx, size_t n) = 0;
-  // dst[i] = src[idx[i]] (src of dtype dt_src) for i < n, in FP64
-  virtual void gather(double* dst, const void* src, int dt_src, const int* idx, size_t n) = 0;
+  // dst[i] = src[idx[i]] + a * x[i] (src of dtype dt_src; x FP64, or null
+  // for no term) for i < n, in FP64
+  virtual void gather(double* dst, const void* src, int dt_src, const int* idx, size_t n, double a = 0.0,
+                      const double* x = nullptr) = 0;
+  // dst[idx[i]] = src[idx[i]] + a rounded to dt_dst, for i < n (src FP64)
+  virtual void shifted_copy_at(void* dst, int dt_dst, const double* src, const int* idx, size_t n, double a) = 0;
   // element-wise precision conversion of n values
   virtual void convert(void* dst, int dt_dst, const void* src, int dt_src, size_t n) = 0;
   // ---- optional: record the calls made between capture_begin and
@@ -135,6 +139,26 @@ class Executor {
   virtual void drop_graph(void* graph) { (void)graph; }
   virtual long long scratch_generation() const { return 0; }
   virtual bool timing_on() const { return false; }
+  // ---- orbital-rotation energy and gradient (orb_grad); all FP64, device arrays
+  // For each of naux symmetric n x n matrices B_L (B + L*n*n), with the
+  // orbitals ordered core (nc), active (na), virtual: scal[4L..4L+3] =
+  // (J, t, q, r) with J = sum_i B_ii (core), t = sum_tu gam_tu B_tu (active),
+  // q = sum_ij B_ij B_ji (core-core), r = sum_{t,u,i} gam_tu B_ti B_iu; and
+  // bact[L*na*na ..] = the active block of B_L, row-major.
+  virtual void orb_scalars(const double* B, int naux, int n, int nc, int na, const double* gam, double* bact,
+                           double* scal) {
+    (void)B; (void)naux; (void)n; (void)nc; (void)na; (void)gam; (void)bact; (void)scal;
+    throw std::runtime_error("executor: no orbital kernels");
+  }
+  // G_L = gradient of the L-sum of 2J^2 - q + 2Jt - r + e2_L with respect to
+  // the n x n entries of B_L, where e2_L = 1/2 bact_L . Y_L, given
+  // Y_L = D bact_L and Z_L = D^T bact_L (naux x na*na each); e2[L] receives e2_L.
+  virtual void orb_assemble(const double* B, int naux, int n, int nc, int na, const double* gam, const double* scal,
+                            const double* bact, const double* Y, const double* Z, double* G, double* e2) {
+    (void)B; (void)naux; (void)n; (void)nc; (void)na; (void)gam; (void)scal; (void)bact; (void)Y; (void)Z;
+    (void)G; (void)e2;
+    throw std::runtime_error("executor: no orbital kernels");
+  }
   // ---- ordering with a caller's stream (a hipStream_t; nullptr = the null
   // stream).  wait_for(s): later work of the executor waits for everything
   // queued on s so far.  signal(s): later work on s waits for everything

@@ -19,6 +19,7 @@
 #include <chrono>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <cstdio>
 #include <type_traits>
@@ -1160,9 +1161,16 @@ __global__ void fill_zero_kernel(unsigned char* p, long long nbytes) {
 
 template <int DS>
 __global__ void gather_kernel(double* __restrict__ dst, const void* __restrict__ src, const int* __restrict__ idx,
-                              long long n) {
+                              long long n, double a, const double* __restrict__ x) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    dst[i] = ldv<DS>(src, idx[i]);
+    dst[i] = x ? ldv<DS>(src, idx[i]) + a * x[i] : ldv<DS>(src, idx[i]);
+}
+
+template <int DD>
+__global__ void shifted_copy_kernel(void* __restrict__ dst, const double* __restrict__ src,
+                                    const int* __restrict__ idx, long long n, double a) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    stv<DD>(dst, idx[i], src[idx[i]] + a);
 }
 
 template <int DS, int DD>
@@ -1235,6 +1243,101 @@ __global__ void precond_kernel(double* t, const double* r, const double* d, doub
     if (fabs(den) < eps) den = den < 0 ? -eps : eps;
     t[j] = r[j] / den;
   }
+}
+
+// ---- orbital-rotation energy terms and their gradient (one work-group per
+// auxiliary index L; n x n matrices, orbitals ordered core, active, virtual)
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(256) void orb_scalars_kernel(const double* __restrict__ Bm, int n, int nc, int na,
+                                                          const double* __restrict__ gam, double* __restrict__ bact,
+                                                          double* __restrict__ scal) {
+  __shared__ double red[256];
+  const int L = blockIdx.x;
+  const double* B = Bm + (long long)L * n * n;
+  double J = 0.0, t = 0.0, q = 0.0, r = 0.0;
+  for (int i = threadIdx.x; i < nc; i += 256) J += B[(long long)i * n + i];
+  for (int e = threadIdx.x; e < na * na; e += 256) {
+    const int a = e / na, b = e % na;
+    const double v = B[(long long)(nc + a) * n + nc + b];
+    bact[(long long)L * na * na + e] = v;
+    t += gam[e] * v;
+  }
+  for (int e = threadIdx.x; e < nc * nc; e += 256) {
+    const int i = e / nc, j = e % nc;
+    q += B[(long long)i * n + j] * B[(long long)j * n + i];
+  }
+  // r = sum_{t,i} B_{c+t,i} (sum_u gam_tu B_{i,c+u})
+  for (int e = threadIdx.x; e < na * nc; e += 256) {
+    const int a = e / nc, i = e % nc;
+    double s = 0.0;
+    for (int u = 0; u < na; ++u) s += gam[a * na + u] * B[(long long)i * n + nc + u];
+    r += B[(long long)(nc + a) * n + i] * s;
+  }
+  J = block_sum(J, red);
+  t = block_sum(t, red);
+  q = block_sum(q, red);
+  r = block_sum(r, red);
+  if (threadIdx.x == 0) {
+    scal[4 * L + 0] = J;
+    scal[4 * L + 1] = t;
+    scal[4 * L + 2] = q;
+    scal[4 * L + 3] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void orb_assemble_kernel(const double* __restrict__ Bm, int n, int nc, int na,
+                                                           const double* __restrict__ gam,
+                                                           const double* __restrict__ scal,
+                                                           const double* __restrict__ bact,
+                                                           const double* __restrict__ Y, const double* __restrict__ Z,
+                                                           double* __restrict__ Gm, double* __restrict__ e2) {
+  __shared__ double red[256];
+  const int L = blockIdx.x;
+  const long long nn = (long long)n * n;
+  const double* B = Bm + L * nn;
+  double* G = Gm + L * nn;
+  const double J = scal[4 * L + 0], t = scal[4 * L + 1];
+  const double* y = Y + (long long)L * na * na;
+  const double* z = Z + (long long)L * na * na;
+  for (long long e = threadIdx.x; e < nn; e += 256) {
+    const int p = (int)(e / n), q = (int)(e % n);
+    const bool pc = p < nc, qc = q < nc;
+    const bool pa = p >= nc && p < nc + na, qa = q >= nc && q < nc + na;
+    double v = 0.0;
+    if (pc && qc) {
+      v = -2.0 * B[(long long)q * n + p];  // d(-q)/dB_pq
+      if (p == q) v += 4.0 * J + 2.0 * t;   // d(2J^2 + 2Jt)/dB_ii
+    } else if (pa && qa) {
+      const int a = p - nc, b = q - nc;
+      v = 2.0 * J * gam[a * na + b] + 0.5 * (y[a * na + b] + z[a * na + b]);
+    } else if (pa && qc) {  // d(-r)/dB_{c+t,i} = -sum_u gam_tu B_{i,c+u}
+      const int a = p - nc;
+      double s = 0.0;
+      for (int u = 0; u < na; ++u) s += gam[a * na + u] * B[(long long)q * n + nc + u];
+      v = -s;
+    } else if (pc && qa) {  // d(-r)/dB_{i,c+u} = -sum_t gam_tu B_{c+t,i}
+      const int b = q - nc;
+      double s = 0.0;
+      for (int a = 0; a < na; ++a) s += gam[a * na + b] * B[(long long)(nc + a) * n + p];
+      v = -s;
+    }
+    G[e] = v;
+  }
+  double s = 0.0;
+  for (int e = threadIdx.x; e < na * na; e += 256) s += bact[(long long)L * na * na + e] * y[e];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) e2[L] = 0.5 * s;
 }
 
 // ---- batched two-sided Jacobi eigensolver, parallel over the whole GPU
@@ -1752,8 +1855,9 @@ class HipExec : public Executor {
   void copy_d2d(void* d, const void* s, size_t b) override {
     if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, stream_));
   }
-  void* prepare(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc) override {
-    Scope sc(t_prep_);
+  // Kernel choice and work items of a launch (host only).
+  Prepared* configure(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc,
+                      std::vector<WorkItem>& items, std::vector<RedItem>& reds) {
     auto* P = new Prepared();
     P->da = da;
     P->db = db;
@@ -1782,14 +1886,27 @@ class HipExec : public Executor {
       P->wave = choose_wave(jobs, terms, 16);
       if (P->wave) P->bm = P->bn = 32;
     }
-    pick(P->mode, da, db, dc, P->kt);  // validate
-    if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
+    try {
+      pick(P->mode, da, db, dc, P->kt);  // validate
+      if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
+      plan_items(jobs, terms, P->kt, P->bm, P->bn, P->wave ? 65536.0 : 16384.0, 64.0, items, reds, P->nslots);
+      P->nitems = (long long)items.size();
+      P->nreds = (long long)reds.size();
+      if (P->nreds) pick_reduce(P->mode, dc);
+    } catch (...) {
+      delete P;
+      throw;
+    }
+    return P;
+  }
+  size_t part_need(const Prepared* P) const {
+    return (size_t)P->nslots * P->bm * P->bn * (P->mode == DT_F64 ? 8 : 4);
+  }
+  void* prepare(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc) override {
+    Scope sc(t_prep_);
     std::vector<WorkItem> items;
     std::vector<RedItem> reds;
-    plan_items(jobs, terms, P->kt, P->bm, P->bn, P->wave ? 65536.0 : 16384.0, 64.0, items, reds, P->nslots);
-    P->nitems = (long long)items.size();
-    P->nreds = (long long)reds.size();
-    if (P->nreds) pick_reduce(P->mode, dc);
+    Prepared* P = configure(jobs, terms, da, db, dc, items, reds);
     if (P->nitems) {
       P->d_jobs = (RawJob*)alloc(jobs.size() * sizeof(RawJob));
       P->d_terms = (RawTerm*)alloc(std::max<size_t>(terms.size(), 1) * sizeof(RawTerm));
@@ -1802,7 +1919,7 @@ class HipExec : public Executor {
         upload(P->d_reds, reds.data(), reds.size() * sizeof(RedItem));
       }
     }
-    const size_t need = (size_t)P->nslots * P->bm * P->bn * (P->mode == DT_F64 ? 8 : 4);
+    const size_t need = part_need(P);
     if (need > part_bytes_) {
       sync();
       if (part_) release(part_);
@@ -1839,7 +1956,8 @@ class HipExec : public Executor {
       KernelFn k = P->padded ? pick_padded(P->dc, P->bm, P->bn) : pick(P->mode, P->da, P->db, P->dc, P->kt);
       for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
         const long long nt = std::min(maxg, P->nitems - t0);
-        hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0, part_);
+        hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0,
+                           part_);
       }
     }
     HIP_OK(hipGetLastError());
@@ -1847,7 +1965,8 @@ class HipExec : public Executor {
       ReduceFn r = pick_reduce(P->mode, P->dc);
       for (long long t0 = 0; t0 < P->nreds; t0 += maxg) {
         const long long nt = std::min(maxg, P->nreds - t0);
-        hipLaunchKernelGGL(r, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_reds + t0, part_, P->bm, P->bn);
+        hipLaunchKernelGGL(r, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_reds + t0,
+                           part_, P->bm, P->bn);
       }
       HIP_OK(hipGetLastError());
     }
@@ -1885,6 +2004,19 @@ class HipExec : public Executor {
     release(P->d_reds);
     delete P;
   }
+  void orb_scalars(const double* B, int naux, int n, int nc, int na, const double* gam, double* bact,
+                   double* scal) override {
+    if (naux <= 0) return;
+    hipLaunchKernelGGL(orb_scalars_kernel, dim3(naux), dim3(256), 0, stream_, B, n, nc, na, gam, bact, scal);
+    HIP_OK(hipGetLastError());
+  }
+  void orb_assemble(const double* B, int naux, int n, int nc, int na, const double* gam, const double* scal,
+                    const double* bact, const double* Y, const double* Z, double* G, double* e2) override {
+    if (naux <= 0) return;
+    hipLaunchKernelGGL(orb_assemble_kernel, dim3(naux), dim3(256), 0, stream_, B, n, nc, na, gam, scal, bact, Y, Z,
+                       G, e2);
+    HIP_OK(hipGetLastError());
+  }
   void sync() override {
     Scope sc(t_sync_);
     HIP_OK(hipStreamSynchronize(stream_));
@@ -1907,13 +2039,24 @@ class HipExec : public Executor {
     else throw std::runtime_error("executor: unsupported pack dtype");
     HIP_OK(hipGetLastError());
   }
-  void gather(double* dst, const void* src, int ds, const int* idx, size_t n) override {
+  void gather(double* dst, const void* src, int ds, const int* idx, size_t n, double a, const double* x) override {
     if (!n) return;
     const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
-    if (ds == DT_F64) hipLaunchKernelGGL((gather_kernel<DT_F64>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
-    else if (ds == DT_F32) hipLaunchKernelGGL((gather_kernel<DT_F32>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
-    else if (ds == DT_BF16) hipLaunchKernelGGL((gather_kernel<DT_BF16>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, (long long)n);
+    const long long nn = (long long)n;
+    if (ds == DT_F64) hipLaunchKernelGGL((gather_kernel<DT_F64>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x);
+    else if (ds == DT_F32) hipLaunchKernelGGL((gather_kernel<DT_F32>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x);
+    else if (ds == DT_BF16) hipLaunchKernelGGL((gather_kernel<DT_BF16>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x);
     else throw std::runtime_error("executor: unsupported gather dtype");
+    HIP_OK(hipGetLastError());
+  }
+  void shifted_copy_at(void* dst, int dd, const double* src, const int* idx, size_t n, double a) override {
+    if (!n) return;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    const long long nn = (long long)n;
+    if (dd == DT_F32) hipLaunchKernelGGL((shifted_copy_kernel<DT_F32>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a);
+    else if (dd == DT_BF16) hipLaunchKernelGGL((shifted_copy_kernel<DT_BF16>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a);
+    else if (dd == DT_F64) hipLaunchKernelGGL((shifted_copy_kernel<DT_F64>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a);
+    else throw std::runtime_error("executor: unsupported shifted copy dtype");
     HIP_OK(hipGetLastError());
   }
   void convert(void* dst, int dd, const void* src, int ds, size_t n) override {

@@ -115,6 +115,12 @@ struct Block {
   // converts before the block meets a left block in H*psi.
   bool normal = false;
   int b = 0, n = 0;
+  // Low-precision copies of the block Hamiltonian (family F_H) hold
+  // H - h_shift * 1: the mean of its diagonal taken out, so that its entries
+  // and the products they feed are rounded relative to the spread of the
+  // block energies rather than their size; H*psi adds the shift back in FP64.
+  double h_shift = 0.0;
+  bool h_shift_set = false;
   Bond bond;
   std::map<std::pair<int, int>, std::unique_ptr<OpLayout>> layouts;
   Family fam[kNumFam];

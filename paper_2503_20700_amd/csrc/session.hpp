@@ -1,7 +1,10 @@
 // Per-context state behind the C ABI: executor, planner context, the H*psi
 // plan of the current two-site block and its device buffers.
 #pragma once
+#include <cstdio>
+#include <cstdlib>
 #include <functional>
+#include <stdexcept>
 #include <memory>
 #include <string>
 #include <vector>
@@ -143,11 +146,69 @@ struct dmrg_ctx {
   static int op_dt(int prec) { return prec == DMRG_FP64 ? dmrg::DT_F64 : prec == DMRG_FP32 ? dmrg::DT_F32 : dmrg::DT_BF16; }
   static int out_dt(int prec) { return prec == DMRG_FP64 ? dmrg::DT_F64 : dmrg::DT_F32; }
 
+  // The low-precision copy of a block's Hamiltonian: H - sigma * 1 with sigma
+  // the mean of its FP64 diagonal (Block::h_shift).
+  void shifted_h_copy(dmrg::Block* blk, int od) {
+    dmrg::Family& F = blk->fam[dmrg::F_H];
+    if (F.buf < 0 || C->ptr(F.buf, od) || F.nops < 1 || std::getenv("DMRG_NO_HSHIFT")) {
+      if (F.buf >= 0) C->ensure_dtype(F.buf, od);
+      return;
+    }
+    C->ensure_dtype(F.buf, od);
+    std::vector<int> diag;
+    for (const auto& b : F.lay->blocks) {
+      if (b.bra != b.ket) continue;
+      const int d = blk->bond.secs[b.bra].dim;
+      for (int i = 0; i < d; ++i) diag.push_back((int)(b.off + (int64_t)i * b.ld + i));
+    }
+    if (diag.empty()) return;
+    if (!blk->h_shift_set) {
+      void* di = ex->alloc(diag.size() * sizeof(int));
+      double* dv = (double*)ex->alloc(diag.size() * 8);
+      ex->upload(di, diag.data(), diag.size() * sizeof(int));
+      ex->gather(dv, C->ptr(F.buf), dmrg::DT_F64, (const int*)di, diag.size());
+      std::vector<double> v(diag.size());
+      ex->download(v.data(), dv, v.size() * 8);
+      double s = 0.0;
+      for (double x : v) s += x;
+      blk->h_shift = s / (double)v.size();
+      blk->h_shift_set = true;
+      ex->release(dv);
+      ex->shifted_copy_at(C->ptr(F.buf, od), od, (const double*)C->ptr(F.buf), (const int*)di, diag.size(),
+                          -blk->h_shift);
+      ex->sync();
+      ex->release(di);
+    } else {
+      void* di = ex->alloc(diag.size() * sizeof(int));
+      ex->upload(di, diag.data(), diag.size() * sizeof(int));
+      ex->shifted_copy_at(C->ptr(F.buf, od), od, (const double*)C->ptr(F.buf), (const int*)di, diag.size(),
+                          -blk->h_shift);
+      ex->sync();
+      ex->release(di);
+    }
+  }
+
+  // What the low-precision H*psi leaves out and end_hpsi adds back in FP64:
+  // the shifts of the block Hamiltonian terms H_L (x) 1 and 1 (x) H_R.
+  double lo_shift() const {
+    double s = 0.0;
+    for (const auto& t : plan->terms) {
+      if (t.hc || t.s1 != dmrg::S_I || t.s2 != dmrg::S_I) continue;
+      if (t.L.fam == dmrg::F_H && t.R.is_id() && C->Lblk->h_shift_set) s += t.c * C->Lblk->h_shift;
+      if (t.R.fam == dmrg::F_H && t.L.is_id() && C->Rblk->h_shift_set) s += t.c * C->Rblk->h_shift;
+    }
+    return s;
+  }
+
   // Operator families and plan buffers in the storage type of precision prec.
   void ready_dtypes(int prec) {
     const int od = op_dt(prec), xd = op_dt(prec), outd = out_dt(prec);
     if (od != dmrg::DT_F64) {
       for (dmrg::Block* blk : {C->Lblk.get(), C->Rblk.get()}) {
+        shifted_h_copy(blk, od);
+        if (std::getenv("DMRG_VERBOSE"))
+          std::fprintf(stderr, "[dmrg] %s block Hamiltonian shift %.6f (%s)\n", blk->left ? "left" : "right",
+                       blk->h_shift, blk->h_shift_set ? "set" : "unset");
         for (int f = 0; f < dmrg::kNumFam; ++f)
           if (blk->fam[f].buf >= 0) C->ensure_dtype(blk->fam[f].buf, od);
         for (auto& t : blk->tmp)
@@ -187,7 +248,10 @@ struct dmrg_ctx {
   // After them: b_out (FP64, caller layout) from b_outp.
   void end_hpsi(dmrg::Executor* e, int prec) {
     const int outd = out_dt(prec);
-    e->gather((double*)C->ptr(b_out), C->ptr(b_outp, outd), outd, (const int*)d_uidx, (size_t)plan->lay.size);
+    const double sh = prec == DMRG_FP64 ? 0.0 : lo_shift();
+    if (std::getenv("DMRG_VERBOSE")) std::fprintf(stderr, "[dmrg] low-precision shift added back: %.6f\n", sh);
+    e->gather((double*)C->ptr(b_out), C->ptr(b_outp, outd), outd, (const int*)d_uidx, (size_t)plan->lay.size, sh,
+              sh != 0.0 ? (const double*)C->ptr(b_in) : nullptr);
   }
 
   // The launches of psi_out = H psi_in on b_in / b_out (prepared already).

@@ -51,6 +51,26 @@ def small_cas(n, seed, naux=None, b_sigma=0.3):
 def huckel_chain(n, seed, naux=None, b_scale=0.3, decay=4.0):
     """Hueckel-like chain: on-site 0, nearest-neighbour hopping -1 Eh, further
     neighbours N(0, 0.02); B^L_pq = b_scale * exp(-|p-q|/decay) * z, z ~ N(0,1)."""
+    h, b = huckel_chain_hb(n, seed, naux, b_scale, decay)
+    return h, _g_from_b(b), b
+
+
+def embedded_cas(n_core=48, n_act=24, n_virt=48, seed=3, naux=None, shift=2.0):
+    """Orbital-gradient workload: the Hueckel-chain recipe over
+    n = n_core + n_act + n_virt orbitals (naux = 3n density-fitting vectors),
+    with the core diagonal of h shifted by -shift and the virtual diagonal by
+    +shift Eh.  Returns (h, B); the four-index g is not formed."""
+    n = n_core + n_act + n_virt
+    h, b = huckel_chain_hb(n, seed, naux)
+    idx = np.arange(n)
+    h[idx[:n_core], idx[:n_core]] -= shift
+    v = idx[n_core + n_act:]
+    h[v, v] += shift
+    return h, b
+
+
+def huckel_chain_hb(n, seed, naux=None, b_scale=0.3, decay=4.0):
+    """h and B of ``huckel_chain`` (same draws, g not formed)."""
     rng = np.random.default_rng(seed)
     naux = 3 * n if naux is None else naux
     h = _sym_from_triu(n, rng.normal(0.0, 0.02, n * (n - 1) // 2), 1)
@@ -61,7 +81,7 @@ def huckel_chain(n, seed, naux=None, b_scale=0.3, decay=4.0):
     dist = np.abs(idx[:, None] - idx[None, :])
     env = b_scale * np.exp(-dist / decay)
     b = np.stack([_sym_from_triu(n, v, 0) for v in rng.normal(0.0, 1.0, (naux, n * (n + 1) // 2))]) * env
-    return h, _g_from_b(b), b
+    return h, b
 
 
 FES_LAYOUT = (("L", 6), ("d", 8), ("L", 12), ("d", 8), ("L", 12), ("d", 8), ("L", 12), ("d", 8), ("L", 8))

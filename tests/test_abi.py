@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2503_20700_amd", "_lib", "libdmrg_mi355x.so")
 
 def declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(dmrg_[a-z_0-9]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b((?:dmrg|orb)_[a-z_0-9]+)\s*\(", txt)))
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="native library not built")

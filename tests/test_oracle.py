@@ -12,6 +12,7 @@ import pytest
 from oracle import fock, heff
 from oracle.cg import cg
 from oracle.mps_fock import Embedding
+from casci import cas_ci_rdms
 from synth.integrals import hubbard_dimer, small_cas
 from synth.mps import LOCAL, SU2MPS, full_counts, psi_layout, random_mps, random_psi
 
@@ -296,59 +297,11 @@ def test_discarded_weight_is_the_truncation_residual():
 
 # ---- orbital rotation energy and gradient (oracle/orbital.py) ----------------------------
 
-def _cas_ci_rdms(h, g, n, n_core, n_act, n_elec_act, seed):
-    """Active-space RDMs of the lowest singlet CAS-CI state (core doubly occupied,
-    virtuals empty), from explicit Jordan-Wigner operators on the active space,
-    and the energy <Psi|H|Psi> of the same state evaluated on the full
-    determinant space."""
-    ncor = n_core
-    a = slice(ncor, ncor + n_act)
-    # effective active Hamiltonian is not needed: diagonalise H on the CAS space directly
-    nu = ncor + n_elec_act // 2
-    dets = fock.sector_dets(n, nu, nu)
-    core_mask = sum(3 << (2 * i) for i in range(ncor))
-    virt_mask = sum(3 << (2 * p) for p in range(ncor + n_act, n))
-    cas = [i for i, d in enumerate(dets) if (d & core_mask) == core_mask and (d & virt_mask) == 0]
-    hm = fock.hamiltonian_sparse(h, g, dets).toarray()[np.ix_(cas, cas)]
-    w, v = np.linalg.eigh(hm)
-    s2, d0 = fock.s2_matrix(n, 2 * nu, 0)
-    s2c = s2.toarray()[np.ix_(cas, cas)]
-    # lowest singlet
-    for j in range(len(w)):
-        if abs(v[:, j] @ s2c @ v[:, j]) < 1e-8:
-            break
-    psi_full = np.zeros(1 << (2 * n))
-    psi_full[np.asarray(dets)[cas]] = v[:, j]
-    # RDMs from literal operators on the full Fock space
-    ops = fock.jw_annihilators(n)
-    ad = [x.T for x in ops]
-    gam = np.zeros((n_act, n_act))
-    Gam = np.zeros((n_act,) * 4)
-    for t in range(n_act):
-        for u in range(n_act):
-            for s in range(2):
-                gam[t, u] += psi_full @ (ad[2 * (ncor + t) + s] @ (ops[2 * (ncor + u) + s] @ psi_full))
-    for t in range(n_act):
-        for u in range(n_act):
-            for vv in range(n_act):
-                for ww in range(n_act):
-                    val = 0.0
-                    for s in range(2):
-                        for r in range(2):
-                            x = ops[2 * (ncor + ww) + s] @ psi_full
-                            x = ops[2 * (ncor + vv) + r] @ x
-                            x = ad[2 * (ncor + u) + r] @ x
-                            x = ad[2 * (ncor + t) + s] @ x
-                            val += psi_full @ x
-                    Gam[t, u, vv, ww] = val
-    return gam, Gam, float(w[j])
-
-
 def test_orbital_energy_at_zero_rotation_is_the_cas_ci_energy():
     from oracle import orbital
     n, n_core, n_act = 5, 1, 3
     h, g, B = small_cas(n, 13)
-    gam, Gam, e_ci = _cas_ci_rdms(h, g, n, n_core, n_act, 4, 0)
+    gam, Gam, e_ci = cas_ci_rdms(h, g, n, n_core, n_act, 4, 0)
     e = orbital.energy(h, B, np.zeros((n, n)), gam, Gam, n_core, n_act)
     assert abs(e - e_ci) < 1e-10
     assert abs(np.trace(gam) - 4.0) < 1e-12
@@ -359,7 +312,7 @@ def test_orbital_gradient_closed_form_equals_finite_differences_and_has_zero_red
     from oracle import orbital
     n, n_core, n_act = 6, 2, 2
     h, g, B = small_cas(n, 3)
-    gam, Gam, _ = _cas_ci_rdms(h, g, n, n_core, n_act, 2, 0)
+    gam, Gam, _ = cas_ci_rdms(h, g, n, n_core, n_act, 2, 0)
     fd = orbital.gradient_fd(h, B, np.zeros((n, n)), gam, Gam, n_core, n_act, step=1e-5)
     cf = orbital.generalized_fock_gradient(h, B, gam, Gam, n_core, n_act)
     assert np.abs(fd - cf).max() < 1e-7 * max(1.0, np.abs(cf).max())
