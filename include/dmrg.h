@@ -148,6 +148,24 @@ int dmrg_hpsi_dev(dmrg_ctx *c, int k, const void *d_in, void *d_out, int prec);
  * its task lists, which waits for the device).  Errors as dmrg_hpsi_dev. */
 int dmrg_hpsi_dev_stream(dmrg_ctx *c, int k, const void *d_in, void *d_out, int prec, void *hip_stream);
 
+/* Allocation-free variant of dmrg_hpsi_dev, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same product, inputs and outputs (device FP64,
+ * n_elems each, caller layout).  Every intermediate of the call -- task
+ * lists, the padded copy of psi, the psi' accumulator, the X intermediates
+ * and split-K partial tiles -- lives in a fixed device array of the library
+ * (128 MiB, one per GPU, held until the process ends, shared by all contexts)
+ * instead of buffers the library allocates; the call allocates no device
+ * memory.  Preconditions: the block's H*psi plan exists (dmrg_psi_layout or
+ * any H*psi call at this block made it) and, for prec != DMRG_FP64, the
+ * operator blocks have their copies in that precision (any earlier H*psi or
+ * Davidson call with it made them).  Returns once d_out is written.  Calls
+ * that overlap on one GPU (other threads or contexts) race on the shared
+ * array.  Errors: ARG (null pointer, bad precision, the preconditions),
+ * BUDGET (the block needs more scratch than the array holds; nothing is
+ * launched), HIP. */
+int dmrg_hpsi_dev_noalloc(dmrg_ctx *c, int k, const void *d_in, void *d_out, int prec);
+
 /* Diagonal of H_eff at the current block (host, n_elems). */
 int dmrg_heff_diag(dmrg_ctx *c, int k, double *diag);
 

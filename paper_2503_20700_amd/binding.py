@@ -75,6 +75,7 @@ def load(path=None):
         "dmrg_stats": (I, [P, dp, I]),
         "dmrg_su2_coefficient": (I, [I, ip, dp]),
         "dmrg_update_opts": (I, [P, ct.POINTER(Opts)]),
+        "dmrg_hpsi_dev_noalloc": (I, [P, I, P, P, I]),
         "orb_grad": (I, [I, I, I, dp, dp, I, dp, dp, dp, dp, dp]),
         "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
         "dmrg_kernel_timing": (I, [P, I, dp, llp]),
@@ -103,7 +104,7 @@ def exported_symbols():
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_truncate_dbss", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
             "dmrg_kernel_timing", "dmrg_current_block", "dmrg_next_guess", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
             "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_batch_davidson", "dmrg_su2_coefficient", "dmrg_update_opts",
-            "orb_grad",
+            "dmrg_hpsi_dev_noalloc", "orb_grad",
             "dmrg_last_error",
             "dmrg_destroy"]
 
@@ -281,6 +282,11 @@ class DMRG:
         else:
             self._check(self.lib.dmrg_hpsi_dev_stream(self._h, self.k, ct.c_void_p(d_in), ct.c_void_p(d_out), prec,
                                                       ct.c_void_p(stream)))
+
+    def hpsi_dev_noalloc(self, d_in, d_out, prec=FP64):
+        """d_out = H d_in on device FP64 buffers through the allocation-free
+        entry point (intermediates in the library's fixed device array)."""
+        self._check(self.lib.dmrg_hpsi_dev_noalloc(self._h, self.k, ct.c_void_p(d_in), ct.c_void_p(d_out), prec))
 
     def heff_diag(self, size):
         out = np.empty(size)

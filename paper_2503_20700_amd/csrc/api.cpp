@@ -309,6 +309,26 @@ extern "C" int dmrg_hpsi_dev_stream(dmrg_ctx* c, int k, const void* din, void* d
   }
 }
 
+extern "C" int dmrg_hpsi_dev_noalloc(dmrg_ctx* c, int k, const void* din, void* dout, int prec) {
+  if (!c || !din || !dout) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_noalloc: null argument");
+  if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_noalloc: no MPS loaded at this k");
+  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_noalloc: bad precision");
+  if (!c->plan)
+    return fail(DMRG_ERR_ARG,
+                "dmrg_hpsi_dev_noalloc: no H*psi plan at this block yet (dmrg_psi_layout or an H*psi call makes it)");
+  if (!c->operators_ready(prec))
+    return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_noalloc: the operator blocks have no copies in this precision yet "
+                              "(an H*psi or Davidson call with it makes them)");
+  try {
+    c->hpsi_fixed(din, dout, prec);
+    return DMRG_OK;
+  } catch (const dmrg_ctx::FixedTooSmall& e) {
+    return fail(DMRG_ERR_BUDGET, std::string("dmrg_hpsi_dev_noalloc: ") + e.what());
+  } catch (const std::exception& e) {
+    return fail(DMRG_ERR_HIP, std::string("dmrg_hpsi_dev_noalloc: ") + e.what());
+  }
+}
+
 extern "C" int dmrg_heff_diag(dmrg_ctx* c, int k, double* diag) {
   if (!c || !diag) return fail(DMRG_ERR_ARG, "dmrg_heff_diag: null argument");
   if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_heff_diag: no MPS loaded at this k");

@@ -159,6 +159,28 @@ class Executor {
     (void)G; (void)e2;
     throw std::runtime_error("executor: no orbital kernels");
   }
+  // ---- fixed scratch of the allocation-free H*psi entry point
+  // Device address and size of this device's fixed scratch array.
+  virtual void* fixed_scratch(size_t* bytes) {
+    *bytes = 0;
+    return nullptr;
+  }
+  // Plan a launch like prepare() without touching device memory: the handle
+  // holds the task lists on the host; *list_bytes / *part_bytes receive the
+  // device bytes its lists and its split-K partial tiles need.
+  virtual void* plan_fixed(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db,
+                           int dc, size_t* list_bytes, size_t* part_bytes) {
+    (void)jobs; (void)terms; (void)da; (void)db; (void)dc; (void)list_bytes; (void)part_bytes;
+    throw std::runtime_error("executor: no fixed scratch");
+  }
+  // Copy a plan_fixed handle's task lists to dev (list_bytes of it) and let
+  // its launches write partial tiles to part; run() then launches it.
+  virtual void place_fixed(void* handle, void* dev, void* part) {
+    (void)handle; (void)dev; (void)part;
+    throw std::runtime_error("executor: no fixed scratch");
+  }
+  // Release a plan_fixed handle (host memory only).
+  virtual void drop_fixed(void* handle) { (void)handle; }
   // ---- ordering with a caller's stream (a hipStream_t; nullptr = the null
   // stream).  wait_for(s): later work of the executor waits for everything
   // queued on s so far.  signal(s): later work on s waits for everything

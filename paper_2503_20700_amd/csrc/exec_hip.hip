@@ -1505,6 +1505,32 @@ __global__ __launch_bounds__(256) void jac_apply(double* __restrict__ A, double*
 // grid's work-item count must fit 32 bits.
 constexpr long long kMaxGroups = 1LL << 23;
 
+// Fixed device scratch of the allocation-free H*psi entry point
+// (dmrg_hpsi_dev_noalloc): one call's task lists, padded operand copy of psi,
+// psi' accumulator, intermediates and partial tiles.  Every GPU the library
+// runs on holds one copy until the process ends; all contexts on a device
+// share it.  Host code reaches it only through the address returned by
+// hipGetSymbolAddress (fixed_scratch_address), never through its name.
+constexpr size_t kFixedScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+// Device address of `scratch` on the current device, looked up once per
+// device and kept.
+void* fixed_scratch_address() {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw std::runtime_error("executor: fixed scratch has no device address");
+  addr[dev] = p;
+  return p;
+}
+
 struct Prepared {
   RawJob* d_jobs = nullptr;
   RawTerm* d_terms = nullptr;
@@ -1515,6 +1541,12 @@ struct Prepared {
   bool padded = false;  // BF16 launch served by gemm_bf16_padded
   bool wave = false;    // ... or by gemm_bf16_wave (32 x 32 tile per wave)
   int bm = TM, bn = TN;  // output tile of the launch
+  void* part = nullptr;  // partial tiles of a fixed-scratch launch (else the executor's)
+  // fixed-scratch launches: task lists kept on the host until placed
+  std::vector<RawJob> h_jobs;
+  std::vector<RawTerm> h_terms;
+  std::vector<WorkItem> h_items;
+  std::vector<RedItem> h_reds;
 };
 
 using KernelFn = void (*)(const RawJob*, const RawTerm*, const WorkItem*, void*);
@@ -1719,7 +1751,10 @@ struct Scope {
 
 class HipExec : public Executor {
  public:
-  HipExec() { HIP_OK(hipStreamCreate(&stream_)); }
+  HipExec() {
+    HIP_OK(hipStreamCreate(&stream_));
+    fixed_ = fixed_scratch_address();
+  }
   ~HipExec() override {
     if (stream_) (void)hipStreamSynchronize(stream_);
     for (auto& b : size_of_) (void)hipFree(b.first);  // live and cached blocks
@@ -1950,14 +1985,14 @@ class HipExec : public Executor {
       for (long long t0 = 0; t0 < P->nitems; t0 += 4 * maxg) {
         const long long nt = std::min(4 * maxg, P->nitems - t0);
         hipLaunchKernelGGL(k, dim3((unsigned)((nt + 3) / 4)), dim3(256), 0, stream_, P->d_jobs, P->d_terms,
-                           P->d_items + t0, part_, nt);
+                           P->d_items + t0, P->part ? P->part : part_, nt);
       }
     } else {
       KernelFn k = P->padded ? pick_padded(P->dc, P->bm, P->bn) : pick(P->mode, P->da, P->db, P->dc, P->kt);
       for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
         const long long nt = std::min(maxg, P->nitems - t0);
         hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0,
-                           part_);
+                           P->part ? P->part : part_);
       }
     }
     HIP_OK(hipGetLastError());
@@ -1966,7 +2001,7 @@ class HipExec : public Executor {
       for (long long t0 = 0; t0 < P->nreds; t0 += maxg) {
         const long long nt = std::min(maxg, P->nreds - t0);
         hipLaunchKernelGGL(r, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_reds + t0,
-                           part_, P->bm, P->bn);
+                           P->part ? P->part : part_, P->bm, P->bn);
       }
       HIP_OK(hipGetLastError());
     }
@@ -2017,6 +2052,35 @@ class HipExec : public Executor {
                        G, e2);
     HIP_OK(hipGetLastError());
   }
+  void* fixed_scratch(size_t* bytes) override {
+    *bytes = kFixedScratchBytes;
+    return fixed_;
+  }
+  void* plan_fixed(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc,
+                   size_t* list_bytes, size_t* part_bytes) override {
+    Scope sc(t_prep_);
+    std::vector<WorkItem> items;
+    std::vector<RedItem> reds;
+    Prepared* P = configure(jobs, terms, da, db, dc, items, reds);
+    P->h_jobs = jobs;
+    P->h_terms = terms;
+    P->h_items.swap(items);
+    P->h_reds.swap(reds);
+    *list_bytes = fixed_layout(P, nullptr);
+    *part_bytes = part_need(P);
+    return P;
+  }
+  void place_fixed(void* h, void* dev, void* part) override {
+    auto* P = (Prepared*)h;
+    fixed_layout(P, (char*)dev);
+    P->part = part;
+    if (!P->nitems) return;
+    upload(P->d_jobs, P->h_jobs.data(), P->h_jobs.size() * sizeof(RawJob));
+    if (!P->h_terms.empty()) upload(P->d_terms, P->h_terms.data(), P->h_terms.size() * sizeof(RawTerm));
+    upload(P->d_items, P->h_items.data(), P->h_items.size() * sizeof(WorkItem));
+    if (P->nreds) upload(P->d_reds, P->h_reds.data(), P->h_reds.size() * sizeof(RedItem));
+  }
+  void drop_fixed(void* h) override { delete (Prepared*)h; }
   void sync() override {
     Scope sc(t_sync_);
     HIP_OK(hipStreamSynchronize(stream_));
@@ -2189,6 +2253,29 @@ class HipExec : public Executor {
   hipStream_t stream() const { return stream_; }
 
  private:
+  // Offsets of a fixed-scratch launch's task lists from base (256-byte
+  // aligned pieces); sets the device pointers if base is given.  Returns the
+  // bytes they span.
+  static size_t fixed_layout(Prepared* P, char* base) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    size_t off = 0;
+    const size_t oj = off;
+    off = al(off + P->h_jobs.size() * sizeof(RawJob));
+    const size_t ot = off;
+    off = al(off + std::max<size_t>(P->h_terms.size(), 1) * sizeof(RawTerm));
+    const size_t oi = off;
+    off = al(off + P->h_items.size() * sizeof(WorkItem));
+    const size_t orr = off;
+    off = al(off + P->h_reds.size() * sizeof(RedItem));
+    if (base) {
+      P->d_jobs = (RawJob*)(base + oj);
+      P->d_terms = (RawTerm*)(base + ot);
+      P->d_items = (WorkItem*)(base + oi);
+      P->d_reds = P->h_reds.empty() ? nullptr : (RedItem*)(base + orr);
+    }
+    return off;
+  }
+  void* fixed_ = nullptr;  // this device's fixed scratch (fixed_scratch_address)
   static unsigned grid1(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
   static size_t round_size(size_t b) {
     if (b == 0) b = 1;

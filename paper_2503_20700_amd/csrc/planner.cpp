@@ -114,9 +114,29 @@ int Context::new_buf(int64_t nel) {
   return (int)bufs.size() - 1;
 }
 
+int Context::view_buf() {
+  DevBuf b;
+  b.view = true;
+  bufs.push_back(b);
+  return (int)bufs.size() - 1;
+}
+
+void Context::set_view(int id, int dt, void* p, int64_t n) {
+  DevBuf& b = bufs[id];
+  if (!b.view) throw std::runtime_error("set_view: not a view buffer");
+  for (auto& q : b.p) q = nullptr;
+  b.p[dt] = p;
+  b.n = n;
+}
+
 void Context::free_buf(int id) {
   if (id < 0 || id >= (int)bufs.size()) return;
   DevBuf& b = bufs[id];
+  if (b.view) {
+    for (auto& q : b.p) q = nullptr;
+    b.n = 0;
+    return;
+  }
   for (int d = 0; d < 4; ++d)
     if (b.p[d]) {
       ex->release(b.p[d]);

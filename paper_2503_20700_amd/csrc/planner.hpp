@@ -102,6 +102,7 @@ struct Family {
 struct DevBuf {
   int64_t n = 0;       // elements
   void* p[4] = {nullptr, nullptr, nullptr, nullptr};  // per dtype copy
+  bool view = false;   // points into memory the buffer does not own
 };
 
 class Context;
@@ -246,6 +247,8 @@ class Context {
   void* ptr(int buf, int dt = DT_F64) const { return bufs[buf].p[dt]; }
   void ensure_dtype(int buf, int dt);  // create converted copy from the F64 master
   void alloc_dtype(int buf, int dt);   // storage in dtype dt, contents undefined
+  int view_buf();                      // entry that points into memory it does not own
+  void set_view(int buf, int dt, void* p, int64_t n);
   int ph[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // placeholder buffers (-1..-7) of the current plan
 
   // MPS

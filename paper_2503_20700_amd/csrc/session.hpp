@@ -265,6 +265,97 @@ struct dmrg_ctx {
     end_hpsi(ex.get(), prec);
   }
 
+  // True if the operator blocks have their copies in the storage type of prec.
+  bool operators_ready(int prec) const {
+    const int od = op_dt(prec);
+    for (const dmrg::Block* blk : {C->Lblk.get(), C->Rblk.get()}) {
+      if (!blk) return false;
+      for (int f = 0; f < dmrg::kNumFam; ++f)
+        if (blk->fam[f].buf >= 0 && C->bufs[blk->fam[f].buf].n > 0 && !C->ptr(blk->fam[f].buf, od)) return false;
+      for (const auto& t : blk->tmp)
+        if (t.buf >= 0 && C->bufs[t.buf].n > 0 && !C->ptr(t.buf, od)) return false;
+    }
+    return true;
+  }
+
+  // d_out = H d_in (device FP64, caller layout) with every intermediate --
+  // task lists, padded copy of psi, psi' accumulator, X and partial tiles --
+  // in the executor's fixed scratch instead of library allocations.  The
+  // plan and the operator copies in prec must exist.  Throws FixedTooSmall
+  // (before any launch) if one call needs more than the scratch holds.
+  struct FixedTooSmall : std::runtime_error {
+    using std::runtime_error::runtime_error;
+  };
+  int v_inp = -1, v_outp = -1, v_x = -1;  // view entries over the fixed scratch
+  void hpsi_fixed(const void* din, void* dout, int prec) {
+    const int od = op_dt(prec), outd = out_dt(prec);
+    size_t cap = 0;
+    char* base = (char*)ex->fixed_scratch(&cap);
+    if (!base) throw std::runtime_error("the executor has no fixed scratch");
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    const dmrg::PsiLayout& lay = plan->lay;
+    const size_t o_inp = 0;
+    const size_t o_outp = al(o_inp + (size_t)lay.psize * dmrg::dtype_size(od));
+    const size_t o_x = al(o_outp + (size_t)lay.size * dmrg::dtype_size(outd));
+    const size_t o_part = al(o_x + (size_t)plan->xmax * dmrg::dtype_size(od));
+    auto too_small = [&](size_t need) {
+      return FixedTooSmall("needs " + std::to_string(need) + " bytes of scratch, the fixed array holds " +
+                           std::to_string(cap) + " (a smaller block, or work_budget_elems, fits it)");
+    };
+    if (o_part > cap) throw too_small(o_part);
+    if (v_inp < 0) {
+      v_inp = C->view_buf();
+      v_outp = C->view_buf();
+      v_x = C->view_buf();
+    }
+    C->set_view(v_inp, od, base + o_inp, lay.psize);
+    C->set_view(v_outp, outd, base + o_outp, lay.size);
+    C->set_view(v_x, od, base + o_x, plan->xmax);
+    C->ph[PH_INP] = v_inp;
+    C->ph[PH_OUTP] = v_outp;
+    C->ph[PH_X] = v_x;
+    std::vector<void*> hs;
+    try {
+      std::vector<size_t> lb;
+      size_t part = 0, lists = 0;
+      for (auto& ch : plan->chunks) {
+        std::vector<dmrg::RawJob> j;
+        std::vector<dmrg::RawTerm> t;
+        size_t l = 0, pb = 0;
+        C->resolve(ch.stageL, j, t, od, od, od);
+        hs.push_back(ex->plan_fixed(j, t, od, od, od, &l, &pb));
+        lb.push_back(l);
+        lists += al(l);
+        part = std::max(part, pb);
+        C->resolve(ch.stageR, j, t, od, od, outd);
+        hs.push_back(ex->plan_fixed(j, t, od, od, outd, &l, &pb));
+        lb.push_back(l);
+        lists += al(l);
+        part = std::max(part, pb);
+      }
+      const size_t o_lists = al(o_part + part);
+      if (o_lists + lists > cap) throw too_small(o_lists + lists);
+      size_t cur = o_lists;
+      for (size_t i = 0; i < hs.size(); ++i) {
+        ex->place_fixed(hs[i], base + cur, base + o_part);
+        cur += al(lb[i]);
+      }
+      ex->pack(base + o_inp, od, (const double*)din, (const int*)d_pidx, (size_t)lay.psize);
+      ex->zero(base + o_outp, (size_t)lay.size * dmrg::dtype_size(outd));
+      for (void* h : hs) ex->run(h);
+      const double sh = prec == DMRG_FP64 ? 0.0 : lo_shift();
+      ex->gather((double*)dout, base + o_outp, outd, (const int*)d_uidx, (size_t)lay.size, sh,
+                 sh != 0.0 ? (const double*)din : nullptr);
+      ex->sync();
+    } catch (...) {
+      for (void* h : hs) ex->drop_fixed(h);
+      bind();
+      throw;
+    }
+    for (void* h : hs) ex->drop_fixed(h);
+    bind();
+  }
+
   // psi_out = H psi_in on the device buffers b_in / b_out (FP64 masters).
   // With opts.hpsi_graph the launch sequence is recorded once per precision
   // and replayed (re-recorded when the executor's scratch moved), except
