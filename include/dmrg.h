@@ -74,7 +74,9 @@ typedef struct {
                                   chunk; 0: default 2^32                           */
   int keep_blocks;             /* 1: keep the operator blocks of every bond that
                                   dmrg_set_mps builds, so dmrg_truncate can move
-                                  the two-site block (memory grows with n)        */
+                                  the two-site block (memory grows with n);
+                                  m >= 2: keep only the m bonds nearest the block
+                                  on each side (m moves); 0: none                 */
   int davidson_refine_iter;    /* iterations of the FP64 refinement phase when
                                   hpsi_prec is not FP64; 0: davidson_max_iter     */
   int davidson_jd_inner;       /* refinement with hpsi_prec not FP64: 0 expands the

@@ -51,6 +51,7 @@ extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, 
   if (o->hpsi_graph < 0 || o->hpsi_graph > 1) return fail(DMRG_ERR_ARG, "dmrg_create: hpsi_graph must be 0 or 1");
   if (o->next_guess < 0 || o->next_guess > 1) return fail(DMRG_ERR_ARG, "dmrg_create: next_guess must be 0 or 1");
   if (o->hbm_budget_bytes < 0) return fail(DMRG_ERR_ARG, "dmrg_create: negative hbm_budget_bytes");
+  if (o->keep_blocks < 0) return fail(DMRG_ERR_ARG, "dmrg_create: negative keep_blocks");
   const size_t n2 = (size_t)n * n, n4 = n2 * n2;
   if (!finite_all(h, n2) || !finite_all(g, n4)) return fail(DMRG_ERR_NONFINITE, "dmrg_create: non-finite integral");
   {
@@ -194,7 +195,10 @@ extern "C" int dmrg_set_mps(dmrg_ctx* c, int k, const int* bs, const int* counts
                    c->ex->host_profile().c_str());
       std::fflush(stderr);
     };
-    const bool keep = c->opts.keep_blocks != 0;
+    // keep_blocks 1: every bond; m >= 2: the m bonds nearest the block on each side
+    const int kb = c->opts.keep_blocks;
+    auto keep_left = [&](int bond) { return kb == 1 || (kb >= 2 && bond >= k - kb); };
+    auto keep_right = [&](int bond) { return kb == 1 || (kb >= 2 && bond <= k + 2 + kb); };
     for (auto& h : C.Lhist)
       if (h) C.free_block(*h);
     for (auto& h : C.Rhist)
@@ -206,7 +210,7 @@ extern "C" int dmrg_set_mps(dmrg_ctx* c, int k, const int* bs, const int* counts
     auto L = C.vacuum_left();
     for (int j = 0; j < k; ++j) {
       auto N = C.grow_left(*L, C.sites[j], C.bonds[j + 1]);
-      if (keep) C.Lhist[j] = std::move(L);
+      if (keep_left(j)) C.Lhist[j] = std::move(L);
       else C.free_block(*L);
       L = std::move(N);
       progress("left", j + 1, *L);
@@ -214,7 +218,7 @@ extern "C" int dmrg_set_mps(dmrg_ctx* c, int k, const int* bs, const int* counts
     auto R = C.vacuum_right();
     for (int j = n - 1; j >= k + 2; --j) {
       auto N = C.grow_right(*R, C.sites[j], C.bonds[j]);
-      if (keep) C.Rhist[j + 1] = std::move(R);
+      if (keep_right(j + 1)) C.Rhist[j + 1] = std::move(R);
       else C.free_block(*R);
       R = std::move(N);
       progress("right", j, *R);

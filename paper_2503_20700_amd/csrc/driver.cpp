@@ -395,9 +395,11 @@ int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* 
     const int lo_iter = c->opts.davidson_lowprec_iter < 0 ? max_iter : c->opts.davidson_lowprec_iter;
     int carried = 1;
     if (prec != DMRG_FP64 && lo_iter > 0) {
-      // phase 1: low-precision matvecs until the residual reaches the
-      // precision's rounding level (relative to the Ritz value) or stalls
-      const double floor_rel = (prec == DMRG_BF16) ? 5e-5 : 1e-7;
+      // phase 1: low-precision matvecs until the residual is small enough
+      // for the FP64 phase to finish in a few tens of iterations (1e-3 of
+      // the spectrum scale for BF16 operands, 1e-6 for FP32), or stalls at
+      // the precision's rounding level
+      const double floor_rel = (prec == DMRG_BF16) ? 1e-3 : 1e-6;
       const double floor_tol = floor_rel * std::max(1.0, std::fabs(diag_scale(c, n)));
       pr = davidson_phase(c, ws, prec, std::max(tol, floor_tol), lo_iter, 0, DMRG_FP64, 1, kStall, refine_keep(c));
       lo = pr.matvecs;
@@ -779,7 +781,8 @@ extern "C" int dmrg_truncate_dbss(dmrg_ctx* c, int k, const double* psi, int dir
     }
     // ---- grow the operator block across the cut, move the two-site block if possible
     c->reset_plan();
-    const bool keep = c->opts.keep_blocks != 0;
+    // blocks left behind are kept for a sweep back only with keep_blocks = 1
+    const bool keep = c->opts.keep_blocks == 1;
     if (dir > 0) {
       auto N = C.grow_left(*C.Lblk, T, nb);
       if (keep) C.Lhist[k] = std::move(C.Lblk);
@@ -789,7 +792,8 @@ extern "C" int dmrg_truncate_dbss(dmrg_ctx* c, int k, const double* psi, int dir
       C.sites[k] = T;
       C.bonds[k + 1] = nb;
       if (k + 3 <= C.n && C.Rhist.size() > (size_t)(k + 3) && C.Rhist[k + 3]) {
-        C.Rhist[k + 2] = std::move(C.Rblk);
+        if (keep) C.Rhist[k + 2] = std::move(C.Rblk);
+        else C.free_block(*C.Rblk);
         C.Rblk = std::move(C.Rhist[k + 3]);
         C.k = k + 1;
       } else {
@@ -804,7 +808,8 @@ extern "C" int dmrg_truncate_dbss(dmrg_ctx* c, int k, const double* psi, int dir
       C.sites[k + 1] = T;
       C.bonds[k + 1] = nb;
       if (k - 1 >= 0 && C.Lhist.size() > (size_t)(k - 1) && C.Lhist[k - 1]) {
-        C.Lhist[k] = std::move(C.Lblk);
+        if (keep) C.Lhist[k] = std::move(C.Lblk);
+        else C.free_block(*C.Lblk);
         C.Lblk = std::move(C.Lhist[k - 1]);
         C.k = k - 1;
       } else {

@@ -150,7 +150,7 @@ struct dmrg_ctx {
   // the mean of its FP64 diagonal (Block::h_shift).
   void shifted_h_copy(dmrg::Block* blk, int od) {
     dmrg::Family& F = blk->fam[dmrg::F_H];
-    if (F.buf < 0 || C->ptr(F.buf, od) || F.nops < 1 || std::getenv("DMRG_NO_HSHIFT")) {
+    if (F.buf < 0 || C->ptr(F.buf, od) || F.nops < 1) {
       if (F.buf >= 0) C->ensure_dtype(F.buf, od);
       return;
     }

@@ -1,7 +1,13 @@
 """Summaries of rocprofv3 CSV output for the H*psi kernels.
 
-    python -m paper_2503_20700_amd.rocprof_summary trace  DIR             # --kernel-trace --stats run
-    python -m paper_2503_20700_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR HPSI_LAUNCHES COPY_MIB OUT.json
+    python rocprof_summary.py trace  DIR             # --kernel-trace --stats run
+    python rocprof_summary.py traffic FETCH_DIR WRITE_DIR HPSI_LAUNCHES COPY_MIB OUT.json
+    python rocprof_summary.py counters DIR HPSI_LAUNCHES OUT.json [ALGORITHMIC_FLOPS]
+
+`counters` sums every counter of one --pmc run over the last HPSI_LAUNCHES
+dispatches of the BF16 grouped GEMMs (executed MFMA flops = 512 per
+SQ_INSTS_VALU_MFMA_MOPS_BF16 MOP) and writes them to OUT.json with the
+kernel source hash.
 
 `trace` prints per-kernel totals of the run and the kernels of its last BF16
 H*psi (bench.py times one BF16 and one FP64 H*psi per step).
@@ -25,7 +31,7 @@ import re
 import sys
 from collections import defaultdict
 
-KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "exec_hip.hip")
+KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2503_20700_amd", "csrc", "exec_hip.hip")
 
 
 def source_sha256() -> str:
@@ -98,7 +104,41 @@ def traffic(fetch_dir: str, write_dir: str, launches: int) -> dict:
     return res
 
 
+def counters(d: str, launches: int) -> dict:
+    """Per-counter sums over the last `launches` dispatches of the BF16 grouped
+    GEMMs in one --pmc run (several counters per dispatch)."""
+    rows = _rows(os.path.join(d, "run_counter_collection.csv"))
+    by_dispatch = defaultdict(dict)
+    name_of = {}
+    for r in rows:
+        di = int(r["Dispatch_Id"])
+        by_dispatch[di][r["Counter_Name"]] = by_dispatch[di].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        name_of[di] = r["Kernel_Name"]
+    gem = [di for di in sorted(by_dispatch) if any(k in name_of[di] for k in BF16_GEMMS)]
+    sel = gem[-launches:]
+    out = defaultdict(float)
+    for di in sel:
+        for k, v in by_dispatch[di].items():
+            out[k] += v
+    return {"kernel": "+".join(BF16_GEMMS), "source_sha256": source_sha256(), "launches": len(sel),
+            "counters": dict(out)}
+
+
 def main(argv):
+    if len(argv) >= 4 and argv[0] == "counters":
+        # counters DIR HPSI_LAUNCHES OUT.json [ALGORITHMIC_FLOPS]
+        res = counters(argv[1], int(argv[2]))
+        c = res["counters"]
+        if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in c:
+            # one MOP is 512 floating-point operations of a BF16 MFMA
+            res["mfma_flops_executed"] = c["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512.0
+            if len(argv) >= 5:
+                res["algorithmic_flops"] = float(argv[4])
+                res["executed_over_algorithmic"] = res["mfma_flops_executed"] / res["algorithmic_flops"]
+        with open(argv[3], "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res, indent=1))
+        return 0
     if len(argv) >= 2 and argv[0] == "trace":
         trace(argv[1])
         return 0

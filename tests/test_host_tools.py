@@ -35,7 +35,7 @@ def _write_counters(path, rows):
 
 
 def test_traffic_scales_counters_by_the_copy_and_sums_the_last_launches(tmp_path):
-    from paper_2503_20700_amd import rocprof_summary as rs
+    import rocprof_summary as rs
     # a 2 MiB copy that the fetch counter reports as half (in KiB), and
     # three GEMM launches of which the last two form the H*psi
     copy_kib = 2 * 1024.0
@@ -63,7 +63,7 @@ def test_bench_reports_traffic_only_for_the_kernel_source_it_was_taken_on():
     # roofline.traffic comes from the committed counter file while its hash
     # matches the executor source, and is null otherwise
     import bench
-    from paper_2503_20700_amd.rocprof_summary import source_sha256
+    from rocprof_summary import source_sha256
     with open(bench.TRAFFIC_FILE) as f:
         t = json.load(f)
     total, detail = bench.measured_traffic("cas82_d4096")
