@@ -269,7 +269,7 @@ def main():
     psi, lay = random_psi(mps, seed=w["seed"] + 1)
     log(f"{w['name']}: MPS drawn in {time.perf_counter() - t0:.1f}s, psi has {psi.size} coefficients")
     dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=BF16, work_budget_elems=args.x_budget,
-              davidson_jd_inner=args.jd_inner)
+              davidson_jd_inner=args.jd_inner, davidson_max_subspace=48)
     bs, cnt = mps.bond_table()
     t0 = time.perf_counter()
     dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())
@@ -385,6 +385,7 @@ def main():
         "fp64_bitwise_reproducible": repro,
         "dmrg_step": step,
         "accuracy_small_complete_space": acc,
+        "tile_autotuner": dm.tuner_report(),
         "setup_s": {"operator_blocks": t_env, "hpsi_plan": t_plan},
         "op_bytes_f64": st["op_bytes"],
         "peak_device_bytes": st["peak_bytes"],

@@ -57,7 +57,14 @@ enum {
   DMRG_ERR_NONFINITE = -7  /* NaN or Inf in an input                             */
 };
 
-typedef enum { DMRG_FP64 = 0, DMRG_FP32 = 1, DMRG_BF16 = 2 } dmrg_prec;
+/* Arithmetic of the H*psi contraction.  FP64: exact path.  FP32 / BF16:
+ * operator blocks, psi and the intermediates stored in that type, FP32
+ * accumulation.  FP8: operator blocks and psi stored as OCP E4M3 with a
+ * power-of-two scale per operator (psi: per call), widened exactly to BF16
+ * for the BF16 MFMA, intermediates in BF16, FP32 accumulation.  The low-
+ * precision copies of the block Hamiltonians hold H minus the mean of their
+ * diagonal, which the product adds back in FP64. */
+typedef enum { DMRG_FP64 = 0, DMRG_FP32 = 1, DMRG_BF16 = 2, DMRG_FP8 = 3 } dmrg_prec;
 
 typedef struct dmrg_ctx dmrg_ctx;
 
@@ -242,6 +249,16 @@ int dmrg_cut_spectrum(dmrg_ctx *c, double *values, int *two_s, int *n, int capac
  * touches (an upper bound that also counts structurally zero rows and unread
  * columns).  n: number of entries wanted (at most 7). */
 int dmrg_stats(dmrg_ctx *c, double *out, int n);
+
+/* The H*psi tile autotuner's choices in this process, as JSON text in buf
+ * (capacity bytes, NUL-terminated): the number of launch classes, how many
+ * were timed here (the rest came from the file DMRG_TUNE_FILE names), and how
+ * many chose each kernel configuration.  The tuner times every candidate
+ * configuration of a padded BF16 H*psi launch (tiles 64x64, 64x128, 128x64
+ * and the one-wave 32x32 kernel) on the launch itself when the plan is first
+ * prepared and keeps the fastest; DMRG_TUNE=0 uses the static rule instead.
+ * Errors: ARG (null, buffer too small). */
+int dmrg_tuner_report(dmrg_ctx *c, char *buf, int capacity);
 
 /* Device-event timing of the library's GEMM launches on its own stream.
  * mode 1: clear and start recording; 0: report and stop; -1: report only.

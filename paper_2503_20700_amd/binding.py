@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_LIB = os.path.join(_HERE, "_lib", "libdmrg_mi355x.so")
 
-FP64, FP32, BF16 = 0, 1, 2
+FP64, FP32, BF16, FP8 = 0, 1, 2, 3
 ERRORS = {-1: "ARG", -2: "SHAPE", -3: "SYMMETRY", -4: "BUDGET", -5: "HIP", -6: "NOCONV", -7: "NONFINITE"}
 
 
@@ -75,6 +75,7 @@ def load(path=None):
         "dmrg_stats": (I, [P, dp, I]),
         "dmrg_su2_coefficient": (I, [I, ip, dp]),
         "dmrg_update_opts": (I, [P, ct.POINTER(Opts)]),
+        "dmrg_tuner_report": (I, [P, ct.c_char_p, I]),
         "dmrg_hpsi_dev_noalloc": (I, [P, I, P, P, I]),
         "orb_grad": (I, [I, I, I, dp, dp, I, dp, dp, dp, dp, dp]),
         "dmrg_gemm_selftest": (I, [I, I, I, dp, I, I, dp, I, I, D, D, dp, I]),
@@ -104,7 +105,7 @@ def exported_symbols():
             "dmrg_davidson_step", "dmrg_truncate", "dmrg_truncate_dbss", "dmrg_cut_spectrum", "dmrg_stats", "dmrg_gemm_selftest",
             "dmrg_kernel_timing", "dmrg_current_block", "dmrg_next_guess", "dmrg_get_bond", "dmrg_get_site", "dmrg_batch_create",
             "dmrg_batch_hpsi", "dmrg_batch_destroy", "dmrg_batch_davidson", "dmrg_su2_coefficient", "dmrg_update_opts",
-            "dmrg_hpsi_dev_noalloc", "orb_grad",
+            "dmrg_hpsi_dev_noalloc", "orb_grad", "dmrg_tuner_report",
             "dmrg_last_error",
             "dmrg_destroy"]
 
@@ -224,6 +225,13 @@ class DMRG:
         if rc != 0:
             raise DMRGError(rc, self.lib.dmrg_last_error().decode())
         return rc
+
+    def tuner_report(self):
+        """The tile autotuner's choices so far (dmrg_tuner_report), as a dict."""
+        import json
+        buf = ct.create_string_buffer(4096)
+        self._check(self.lib.dmrg_tuner_report(self._h, buf, 4096))
+        return json.loads(buf.value.decode()) if buf.value else {}
 
     def update_opts(self, **kw):
         """Change Davidson / precision / graph / next-guess options in place

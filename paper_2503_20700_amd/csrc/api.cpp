@@ -44,7 +44,7 @@ extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, 
   if (o->n_elec < 0 || o->n_elec > 2 * n) return fail(DMRG_ERR_SYMMETRY, "dmrg_create: N out of range");
   if (o->two_s < 0 || ((o->n_elec + o->two_s) & 1) || o->two_s > std::min(o->n_elec, 2 * n - o->n_elec))
     return fail(DMRG_ERR_SYMMETRY, "dmrg_create: 2S incompatible with N");
-  if (o->hpsi_prec < 0 || o->hpsi_prec > 2) return fail(DMRG_ERR_ARG, "dmrg_create: bad hpsi_prec");
+  if (o->hpsi_prec < 0 || o->hpsi_prec > 3) return fail(DMRG_ERR_ARG, "dmrg_create: bad hpsi_prec");
   if (o->davidson_max_iter < 0 || o->davidson_refine_iter < 0 || o->davidson_max_subspace < 0 ||
       o->davidson_jd_inner < 0 || o->davidson_lowprec_iter < -1)
     return fail(DMRG_ERR_ARG, "dmrg_create: negative Davidson budget");
@@ -103,7 +103,7 @@ extern "C" int dmrg_update_opts(dmrg_ctx* c, const dmrg_opts* o) {
       o->work_budget_elems != p.work_budget_elems || o->keep_blocks != p.keep_blocks ||
       o->hbm_budget_bytes != p.hbm_budget_bytes || o->e_core != p.e_core)
     return fail(DMRG_ERR_ARG, "dmrg_update_opts: only the Davidson, precision, graph and next-guess fields may change");
-  if (o->hpsi_prec < 0 || o->hpsi_prec > 2) return fail(DMRG_ERR_ARG, "dmrg_update_opts: bad hpsi_prec");
+  if (o->hpsi_prec < 0 || o->hpsi_prec > 3) return fail(DMRG_ERR_ARG, "dmrg_update_opts: bad hpsi_prec");
   if (o->davidson_max_iter < 0 || o->davidson_refine_iter < 0 || o->davidson_max_subspace < 0 ||
       o->davidson_jd_inner < 0 || o->davidson_lowprec_iter < -1 || !(o->davidson_tol >= 0.0))
     return fail(DMRG_ERR_ARG, "dmrg_update_opts: negative Davidson budget or tolerance");
@@ -258,7 +258,7 @@ extern "C" int dmrg_psi_layout(dmrg_ctx* c, int k, long long* nsb, long long* de
 extern "C" int dmrg_hpsi(dmrg_ctx* c, int k, const double* in, double* out, int prec, double* flops) {
   if (!c || !in || !out) return fail(DMRG_ERR_ARG, "dmrg_hpsi: null argument");
   if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_hpsi: no MPS loaded at this k");
-  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "dmrg_hpsi: bad precision");
+  if (prec < 0 || prec > 3) return fail(DMRG_ERR_ARG, "dmrg_hpsi: bad precision");
   try {
     c->ensure_plan();
     const int64_t n = c->plan->lay.size;
@@ -278,7 +278,7 @@ extern "C" int dmrg_hpsi(dmrg_ctx* c, int k, const double* in, double* out, int 
 extern "C" int dmrg_hpsi_dev(dmrg_ctx* c, int k, const void* din, void* dout, int prec) {
   if (!c || !din || !dout) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev: null argument");
   if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev: no MPS loaded at this k");
-  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev: bad precision");
+  if (prec < 0 || prec > 3) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev: bad precision");
   try {
     c->ensure_plan();
     const int64_t n = c->plan->lay.size;
@@ -296,7 +296,7 @@ extern "C" int dmrg_hpsi_dev(dmrg_ctx* c, int k, const void* din, void* dout, in
 extern "C" int dmrg_hpsi_dev_stream(dmrg_ctx* c, int k, const void* din, void* dout, int prec, void* hip_stream) {
   if (!c || !din || !dout) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_stream: null argument");
   if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_stream: no MPS loaded at this k");
-  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_stream: bad precision");
+  if (prec < 0 || prec > 3) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_stream: bad precision");
   try {
     c->ensure_plan();
     const int64_t n = c->plan->lay.size;
@@ -316,7 +316,8 @@ extern "C" int dmrg_hpsi_dev_stream(dmrg_ctx* c, int k, const void* din, void* d
 extern "C" int dmrg_hpsi_dev_noalloc(dmrg_ctx* c, int k, const void* din, void* dout, int prec) {
   if (!c || !din || !dout) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_noalloc: null argument");
   if (!c->C->Lblk || k != c->C->k) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_noalloc: no MPS loaded at this k");
-  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_noalloc: bad precision");
+  if (prec < 0 || prec > 2)
+    return fail(DMRG_ERR_ARG, "dmrg_hpsi_dev_noalloc: bad precision (FP64, FP32 or BF16; FP8 needs dmrg_hpsi_dev)");
   if (!c->plan)
     return fail(DMRG_ERR_ARG,
                 "dmrg_hpsi_dev_noalloc: no H*psi plan at this block yet (dmrg_psi_layout or an H*psi call makes it)");
@@ -370,15 +371,30 @@ extern "C" int dmrg_gemm_selftest(int m, int n, int k, const double* A, int ta, 
                                   int ib, double alpha, double beta, double* C, int prec) {
   if (m <= 0 || n <= 0 || k <= 0 || !C || (!ia && !A) || (!ib && !B)) return fail(DMRG_ERR_ARG, "gemm_selftest: bad args");
   if ((ia && k != m) || (ib && k != n)) return fail(DMRG_ERR_SHAPE, "gemm_selftest: identity needs k == m / n");
-  if (prec < 0 || prec > 2) return fail(DMRG_ERR_ARG, "gemm_selftest: bad precision");
+  if (prec < 0 || prec > 3) return fail(DMRG_ERR_ARG, "gemm_selftest: bad precision");
+  if (prec == DMRG_FP8 && ((!ia && !(ta & 2)) || (!ib && !(tb & 2))))
+    return fail(DMRG_ERR_ARG, "gemm_selftest: FP8 operands must be stored padded (bit 1 of trans)");
   try {
     std::unique_ptr<Executor> ex(make_hip_executor());
-    const int dt = prec == DMRG_FP64 ? DT_F64 : prec == DMRG_FP32 ? DT_F32 : DT_BF16;
+    const int dt = prec == DMRG_FP64 ? DT_F64 : prec == DMRG_FP32 ? DT_F32 : prec == DMRG_FP8 ? DT_FP8 : DT_BF16;
     const int dc = prec == DMRG_FP64 ? DT_F64 : DT_F32;
+    double fp8_scale = 1.0;  // product of the operands' FP8 scales
     auto put = [&](const double* h, size_t cnt, int d) -> void* {
       void* p64 = ex->alloc(cnt * 8);
       ex->upload(p64, h, cnt * 8);
       if (d == DT_F64) return p64;
+      if (d == DT_FP8) {  // one power-of-two scale for the whole operand
+        double* sc = (double*)ex->alloc(2 * sizeof(double));
+        ex->fp8_scales((const double*)p64, 1, (int64_t)cnt, sc);
+        void* p = ex->alloc(cnt);
+        ex->to_fp8(p, (const double*)p64, (int64_t)cnt, (int64_t)cnt, sc);
+        double hs[2];
+        ex->download(hs, sc, sizeof hs);
+        fp8_scale *= hs[0];
+        ex->release(sc);
+        ex->release(p64);
+        return p;
+      }
       void* p = ex->alloc(cnt * dtype_size(d));
       ex->convert(p, d, p64, DT_F64, cnt);
       ex->sync();
@@ -406,6 +422,7 @@ extern "C" int dmrg_gemm_selftest(int m, int n, int k, const double* A, int ta, 
     std::vector<double> cb((size_t)m * n);
     for (size_t i = 0; i < cb.size(); ++i) cb[i] = beta * C[i];
     void* dC = put(cb.data(), cb.size(), dc);
+    alpha *= fp8_scale;
     RawJob j{dC, m, n, n, 1, 0, 0, 1};
     RawTerm t{dA, dB, ldA, ldB, k,
               (ta ? TF_TRANS_A : 0) | (tb ? TF_TRANS_B : 0) | (ia ? TF_IDENT_A : 0) | (ib ? TF_IDENT_B : 0) |
@@ -443,6 +460,13 @@ extern "C" int dmrg_su2_coefficient(int kind, const int* two_j, double* value) {
     *value = ninej2(two_j[0], two_j[1], two_j[2], two_j[3], two_j[4], two_j[5], two_j[6], two_j[7], two_j[8]);
   else return fail(DMRG_ERR_ARG, "dmrg_su2_coefficient: kind must be 0 (CG), 1 (6j) or 2 (9j)");
   return DMRG_OK;
+}
+
+extern "C" int dmrg_tuner_report(dmrg_ctx* c, char* buf, int capacity) {
+  if (!c || !buf || capacity < 1) return fail(DMRG_ERR_ARG, "dmrg_tuner_report: null argument or no capacity");
+  const std::string r = c->ex->tuner_report();
+  std::snprintf(buf, (size_t)capacity, "%s", r.c_str());
+  return (int)r.size() < capacity ? DMRG_OK : fail(DMRG_ERR_ARG, "dmrg_tuner_report: buffer too small");
 }
 
 extern "C" int dmrg_stats(dmrg_ctx* c, double* out, int n) {

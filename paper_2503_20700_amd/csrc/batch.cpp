@@ -57,7 +57,7 @@ void merge(dmrg_batch* b, Merged& M, size_t c, bool left, int dta, int dtb, int 
     jobs.insert(jobs.end(), j.begin(), j.end());
     terms.insert(terms.end(), t.begin(), t.end());
   }
-  void* h = b->ex->prepare(jobs, terms, dta, dtb, dtc);
+  void* h = b->ex->prepare_tuned(jobs, terms, dta, dtb, dtc);
   (left ? M.stageL : M.stageR).push_back(h);
 }
 
@@ -73,10 +73,10 @@ Merged& merged_for(dmrg_batch* b, int prec) {
     nchunks = std::max(nchunks, x->plan->chunks.size());
   }
   Merged& M = b->merged[prec];
-  const int od = dmrg_ctx::op_dt(prec), outd = dmrg_ctx::out_dt(prec);
+  const int od = dmrg_ctx::op_dt(prec), xd = dmrg_ctx::x_dt(prec), outd = dmrg_ctx::out_dt(prec);
   for (size_t c = 0; c < nchunks; ++c) {
-    merge(b, M, c, true, od, od, od);
-    merge(b, M, c, false, od, od, outd);
+    merge(b, M, c, true, od, od, xd);
+    merge(b, M, c, false, xd, od, outd);
   }
   return M;
 }
@@ -205,7 +205,7 @@ struct Rendezvous {
 
 extern "C" int dmrg_batch_create(dmrg_ctx* const* ctxs, int count, int prec, dmrg_batch** out) {
   if (!ctxs || !out || count < 1) return dmrg_fail(DMRG_ERR_ARG, "dmrg_batch_create: bad arguments");
-  if (prec < 0 || prec > 2) return dmrg_fail(DMRG_ERR_ARG, "dmrg_batch_create: bad precision");
+  if (prec < 0 || prec > 3) return dmrg_fail(DMRG_ERR_ARG, "dmrg_batch_create: bad precision");
   *out = nullptr;
   for (int i = 0; i < count; ++i) {
     if (!ctxs[i]) return dmrg_fail(DMRG_ERR_ARG, "dmrg_batch_create: null context");

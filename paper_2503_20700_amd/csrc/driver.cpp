@@ -397,9 +397,9 @@ int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* 
     if (prec != DMRG_FP64 && lo_iter > 0) {
       // phase 1: low-precision matvecs until the residual is small enough
       // for the FP64 phase to finish in a few tens of iterations (1e-3 of
-      // the spectrum scale for BF16 operands, 1e-6 for FP32), or stalls at
-      // the precision's rounding level
-      const double floor_rel = (prec == DMRG_BF16) ? 1e-3 : 1e-6;
+      // the spectrum scale for BF16 operands, 1e-2 for FP8, 1e-6 for FP32),
+      // or stalls at the precision's rounding level
+      const double floor_rel = prec == DMRG_BF16 ? 1e-3 : prec == DMRG_FP8 ? 1e-2 : 1e-6;
       const double floor_tol = floor_rel * std::max(1.0, std::fabs(diag_scale(c, n)));
       pr = davidson_phase(c, ws, prec, std::max(tol, floor_tol), lo_iter, 0, DMRG_FP64, 1, kStall, refine_keep(c));
       lo = pr.matvecs;

@@ -85,6 +85,15 @@ class Executor {
   // dtype tout (both F64 for the exact path).  Returns an opaque handle.
   virtual void* prepare(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int tin_a,
                         int tin_b, int tout) = 0;
+  // Like prepare(), choosing the kernel configuration of the launch by timing
+  // the candidates on it (the outputs it writes while doing so are scratch);
+  // executors without a tuner prepare with their static rule.
+  virtual void* prepare_tuned(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int tin_a,
+                              int tin_b, int tout) {
+    return prepare(jobs, terms, tin_a, tin_b, tout);
+  }
+  // The tuner's choices so far (JSON object text; empty if there is no tuner).
+  virtual std::string tuner_report() const { return std::string(); }
   virtual void run(void* handle) = 0;
   virtual void drop(void* handle) = 0;
   virtual void sync() = 0;
@@ -121,7 +130,26 @@ class Executor {
   // dst[i] = src[idx[i]] + a * x[i] (src of dtype dt_src; x FP64, or null
   // for no term) for i < n, in FP64
   virtual void gather(double* dst, const void* src, int dt_src, const int* idx, size_t n, double a = 0.0,
-                      const double* x = nullptr) = 0;
+                      const double* x = nullptr, const double* mul = nullptr) = 0;
+  // ---- FP8 (OCP E4M3) copies with power-of-two scales
+  // d_scale[2y], d_scale[2y+1] = (s, 1/s) of segment y of src (nseg segments
+  // of seg values): s = 2^e, the smallest with max|x| / s <= 448 (1 for zeros)
+  virtual void fp8_scales(const double* src, int64_t nseg, int64_t seg, double* d_scale) {
+    (void)src; (void)nseg; (void)seg; (void)d_scale;
+    throw std::runtime_error("executor: no FP8 support");
+  }
+  // dst[i] = E4M3(src[i] / s of segment i / seg), round to nearest even, saturating
+  virtual void to_fp8(void* dst, const double* src, int64_t n, int64_t seg, const double* d_scale) {
+    (void)dst; (void)src; (void)n; (void)seg; (void)d_scale;
+    throw std::runtime_error("executor: no FP8 support");
+  }
+  // d_scale[0..1] = (s, 1/s) of the n_all values at src_all, then
+  // dst[i] = idx[i] >= 0 ? E4M3(src[idx[i]] / s) : 0 for i < n
+  virtual void pack_fp8(void* dst, const double* src, const int* idx, size_t n, double* d_scale,
+                        const double* src_all, size_t n_all) {
+    (void)dst; (void)src; (void)idx; (void)n; (void)d_scale; (void)src_all; (void)n_all;
+    throw std::runtime_error("executor: no FP8 support");
+  }
   // dst[idx[i]] = src[idx[i]] + a rounded to dt_dst, for i < n (src FP64)
   virtual void shifted_copy_at(void* dst, int dt_dst, const double* src, const int* idx, size_t n, double a) = 0;
   // element-wise precision conversion of n values

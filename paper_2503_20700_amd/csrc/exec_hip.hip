@@ -53,6 +53,24 @@ constexpr int TM = 64, TN = 64;
 __device__ __forceinline__ u16 f2bf(float f) { return __builtin_bit_cast(u16, (__bf16)f); }
 __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float(((unsigned int)h) << 16); }
 
+// FP8 (OCP E4M3) storage.  Every E4M3 value is exactly a BF16 value, so FP8
+// operands are widened to BF16 as they are loaded and multiplied on the BF16
+// MFMA; the FP8 copies halve the operand bytes the kernels move.
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned bf16x2_of(f2v f) { return (unsigned)f2bf(f[0]) | ((unsigned)f2bf(f[1]) << 16); }
+__device__ __forceinline__ uint4 fp8x8_to_bf16x8(uint2 x) {
+  return make_uint4(bf16x2_of(__builtin_amdgcn_cvt_pk_f32_fp8((int)x.x, false)),
+                    bf16x2_of(__builtin_amdgcn_cvt_pk_f32_fp8((int)x.x, true)),
+                    bf16x2_of(__builtin_amdgcn_cvt_pk_f32_fp8((int)x.y, false)),
+                    bf16x2_of(__builtin_amdgcn_cvt_pk_f32_fp8((int)x.y, true)));
+}
+__device__ __forceinline__ float fp8_to_f(unsigned char b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
+// round to nearest even E4M3, saturating at +-448
+__device__ __forceinline__ unsigned char f_to_fp8(float v) {
+  v = fminf(fmaxf(v, -448.f), 448.f);
+  return (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.f, 0, false) & 0xff);
+}
+
 template <int DT>
 __device__ __forceinline__ double ldv(const void* p, long long i) {
   if constexpr (DT == DT_F64) return ((const double*)p)[i];
@@ -524,7 +542,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
 // the register budget is capped to keep more waves resident: 7 per SIMD for
 // 64 x 64 tiles and 4 for the larger ones, the most that compile without
 // spilling to scratch.
-template <int DC, int BM, int BN>
+template <int DC, int BM, int BN, bool AF8 = false, bool BF8 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4096 ? 4 : 7))) void gemm_bf16_padded(const RawJob* __restrict__ jobs,
                                                         const RawTerm* __restrict__ terms,
                                                         const WorkItem* __restrict__ items, void* __restrict__ part) {
@@ -556,7 +574,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4
       if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
       const RawTerm T = terms[t];
       const bool ia = fl & TF_IDENT_A;
-      const u16* P = (const u16*)(ia ? T.B : T.A);
+      const void* P = ia ? T.B : T.A;
+      const bool f8 = ia ? BF8 : AF8;
       const long long ld = ia ? T.ldb : T.lda;
       const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
 #pragma unroll
@@ -567,8 +586,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4
           for (int v = 0; v < 4; ++v) {
             const int row = m0 + wm + a * 16 + 4 * lg + v;
             const int col = n0 + wn + b * 16 + lr;
-            if (row < J.m && col < J.n)
-              acc[a][b][v] += (float)T.alpha * bf2f(P[tr ? (long long)col * ld + row : (long long)row * ld + col]);
+            if (row < J.m && col < J.n) {
+              const long long e = tr ? (long long)col * ld + row : (long long)row * ld + col;
+              acc[a][b][v] += (float)T.alpha * (f8 ? fp8_to_f(((const unsigned char*)P)[e]) : bf2f(((const u16*)P)[e]));
+            }
           }
     }
   auto lds_at = [](int j, int k) { return j * LS + 8 * ((k >> 3) ^ ((j >> 4) & 3)) + (k & 7); };
@@ -596,9 +617,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4
     for (int q = 0; q < 8; ++q) offBM[v][q] = lds_at(vBM[v] + q, kBM[v]);
   }
 
-  // load cursor (product whose slabs are being loaded)
-  const u16* pa[NA];
-  const u16* pb[NB];
+  // load cursor (product whose slabs are being loaded), in bytes; FP8
+  // operands have 1-byte elements
+  constexpr int ESA = AF8 ? 1 : 2, ESB = BF8 ? 1 : 2;
+  const unsigned char* pa[NA];
+  const unsigned char* pb[NB];
   long long stepA = 0, stepB = 0;
   bool aK = true, bK = true;
   bool okA[NA], okB[NB];
@@ -606,44 +629,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4
   auto begin = [&](const RawTerm& T) {
     aK = !(T.flags & TF_TRANS_A);  // A stored m x k (k contiguous)
     bK = (T.flags & TF_TRANS_B);   // B stored n x k (k contiguous)
-    const u16* A = (const u16*)T.A;
-    const u16* B = (const u16*)T.B;
+    const unsigned char* A = (const unsigned char*)T.A;
+    const unsigned char* B = (const unsigned char*)T.B;
 #pragma unroll
     for (int v = 0; v < NA; ++v) {
       const int vi = tid + 256 * v;
       if (aK) {
         okA[v] = m0 + (vi >> 2) < J.m;
-        pa[v] = A + (long long)(m0 + (vi >> 2)) * T.lda + kvK;
+        pa[v] = A + ((long long)(m0 + (vi >> 2)) * T.lda + kvK) * ESA;
       } else {
         nvA[v] = min(max(J.m - (m0 + vAM[v]), 0), 8);
-        pa[v] = A + (long long)kAM[v] * T.lda + m0 + vAM[v];
+        pa[v] = A + ((long long)kAM[v] * T.lda + m0 + vAM[v]) * ESA;
       }
     }
-    stepA = aK ? KT : (long long)KT * T.lda;
+    stepA = (aK ? KT : (long long)KT * T.lda) * ESA;
 #pragma unroll
     for (int v = 0; v < NB; ++v) {
       const int vi = tid + 256 * v;
       if (bK) {
         okB[v] = n0 + (vi >> 2) < J.n;
-        pb[v] = B + (long long)(n0 + (vi >> 2)) * T.ldb + kvK;
+        pb[v] = B + ((long long)(n0 + (vi >> 2)) * T.ldb + kvK) * ESB;
       } else {
         nvB[v] = min(max(J.n - (n0 + vBM[v]), 0), 8);
-        pb[v] = B + (long long)kBM[v] * T.ldb + n0 + vBM[v];
+        pb[v] = B + ((long long)kBM[v] * T.ldb + n0 + vBM[v]) * ESB;
       }
     }
-    stepB = bK ? KT : (long long)KT * T.ldb;
+    stepB = (bK ? KT : (long long)KT * T.ldb) * ESB;
   };
   uint4 ra[NA], rb[NB];
   const uint4 z4 = make_uint4(0, 0, 0, 0);
+  // 8 elements at p: a 16-byte vector of BF16, or 8 FP8 bytes widened to BF16
+  auto vec8 = [&](const unsigned char* p, bool f8) -> uint4 {
+    if (f8) return fp8x8_to_bf16x8(*(const uint2*)p);
+    return *(const uint4*)p;
+  };
   auto load = [&](int K, int k0) {
     const int nvk = K - (k0 + kvK);  // valid k in this thread's vector ("K" role)
 #pragma unroll
     for (int v = 0; v < NA; ++v) {
       if (aK) {
-        ra[v] = (okA[v] && nvk > 0) ? *(const uint4*)pa[v] : z4;
+        ra[v] = (okA[v] && nvk > 0) ? vec8(pa[v], AF8) : z4;
         if (nvk < 8) ra[v] = keep_first<2>(ra[v], nvk);
       } else {
-        ra[v] = (k0 + kAM[v] < K && nvA[v] > 0) ? *(const uint4*)pa[v] : z4;
+        ra[v] = (k0 + kAM[v] < K && nvA[v] > 0) ? vec8(pa[v], AF8) : z4;
         if (nvA[v] < 8) ra[v] = keep_first<2>(ra[v], nvA[v]);
       }
       pa[v] += stepA;
@@ -651,10 +679,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4
 #pragma unroll
     for (int v = 0; v < NB; ++v) {
       if (bK) {
-        rb[v] = (okB[v] && nvk > 0) ? *(const uint4*)pb[v] : z4;
+        rb[v] = (okB[v] && nvk > 0) ? vec8(pb[v], BF8) : z4;
         if (nvk < 8) rb[v] = keep_first<2>(rb[v], nvk);
       } else {
-        rb[v] = (k0 + kBM[v] < K && nvB[v] > 0) ? *(const uint4*)pb[v] : z4;
+        rb[v] = (k0 + kBM[v] < K && nvB[v] > 0) ? vec8(pb[v], BF8) : z4;
         if (nvB[v] < 8) rb[v] = keep_first<2>(rb[v], nvB[v]);
       }
       pb[v] += stepB;
@@ -1161,9 +1189,58 @@ __global__ void fill_zero_kernel(unsigned char* p, long long nbytes) {
 
 template <int DS>
 __global__ void gather_kernel(double* __restrict__ dst, const void* __restrict__ src, const int* __restrict__ idx,
-                              long long n, double a, const double* __restrict__ x) {
+                              long long n, double a, const double* __restrict__ x, const double* __restrict__ mul) {
+  const double m = mul ? mul[0] : 1.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    dst[i] = x ? ldv<DS>(src, idx[i]) + a * x[i] : ldv<DS>(src, idx[i]);
+    dst[i] = x ? m * ldv<DS>(src, idx[i]) + a * x[i] : m * ldv<DS>(src, idx[i]);
+}
+
+// ---- FP8 copies.  Power-of-two scales s, chosen so that max|x| / s <= 448
+// (the largest finite E4M3 value): the stored values are x / s rounded to
+// E4M3, and s is applied exactly in FP32/FP64 elsewhere.
+__global__ __launch_bounds__(256) void absmax_partial(const double* __restrict__ x, long long n, long long stride,
+                                                      double* __restrict__ part) {
+  // one work-group per (segment blockIdx.y, slice blockIdx.x) of the segments [y*stride, y*stride + n)
+  __shared__ double red[256];
+  const double* p = x + (long long)blockIdx.y * stride;
+  double m = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) m = fmax(m, fabs(p[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// scale[y] = (s, 1/s) of segment y from its gridDim-wide partial maxima
+__global__ void pow2_scale(const double* __restrict__ part, int nb, int nseg, double* __restrict__ scale) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= nseg) return;
+  double m = 0.0;
+  for (int i = 0; i < nb; ++i) m = fmax(m, part[(long long)y * nb + i]);
+  int e = 0;
+  if (m > 0.0) {
+    (void)frexp(m / 448.0, &e);  // m / 448 = f * 2^e, f in [0.5, 1): m / 2^e <= 448
+  }
+  scale[2 * y] = ldexp(1.0, e);
+  scale[2 * y + 1] = ldexp(1.0, -e);
+}
+
+__global__ void to_fp8_kernel(unsigned char* __restrict__ dst, const double* __restrict__ src, long long n,
+                              long long seg, const double* __restrict__ scale) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = f_to_fp8((float)(src[i] * scale[2 * (i / seg) + 1]));
+}
+
+__global__ void pack_fp8_kernel(unsigned char* __restrict__ dst, const double* __restrict__ src,
+                                const int* __restrict__ idx, long long n, const double* __restrict__ scale) {
+  const double inv = scale[1];
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int j = idx[i];
+    dst[i] = j >= 0 ? f_to_fp8((float)(src[j] * inv)) : (unsigned char)0;
+  }
 }
 
 template <int DD>
@@ -1562,13 +1639,19 @@ KernelFn pick(int mode, int da, int db, int dc, int kt) {
   throw std::runtime_error("executor: unsupported dtype combination");
 }
 
-KernelFn pick_padded(int dc, int bm, int bn) {
-#define P_(D, M, N) \
-  if (dc == D && bm == M && bn == N) return gemm_bf16_padded<D, M, N>;
-  P_(DT_BF16, 64, 64) P_(DT_BF16, 64, 128) P_(DT_BF16, 128, 64)
-  P_(DT_F32, 64, 64) P_(DT_F32, 64, 128) P_(DT_F32, 128, 64)
+KernelFn pick_padded(int dc, int bm, int bn, bool af8 = false, bool bf8 = false) {
+#define P_(D, M, N, FA, FB) \
+  if (dc == D && bm == M && bn == N && af8 == FA && bf8 == FB) return gemm_bf16_padded<D, M, N, FA, FB>;
+  P_(DT_BF16, 64, 64, false, false) P_(DT_BF16, 64, 128, false, false) P_(DT_BF16, 128, 64, false, false)
+  P_(DT_F32, 64, 64, false, false) P_(DT_F32, 64, 128, false, false) P_(DT_F32, 128, 64, false, false)
+  // FP8 operands: stage L (operator blocks and psi in FP8, X out in BF16),
+  // stage R (X in BF16, operator blocks in FP8, psi' out in FP32)
+  P_(DT_BF16, 64, 64, true, true) P_(DT_BF16, 64, 128, true, true) P_(DT_BF16, 128, 64, true, true)
+  P_(DT_F32, 64, 64, false, true) P_(DT_F32, 64, 128, false, true) P_(DT_F32, 128, 64, false, true)
+  // (and the self-test's FP8 x FP8 into FP32)
+  P_(DT_F32, 64, 64, true, true) P_(DT_F32, 64, 128, true, true) P_(DT_F32, 128, 64, true, true)
 #undef P_
-  throw std::runtime_error("executor: unsupported tile shape");
+  throw std::runtime_error("executor: unsupported tile shape or FP8 operand combination");
 }
 
 // Output tile of a padded BF16 launch.  Candidates 64x64, 64x128 and 128x64:
@@ -1891,30 +1974,45 @@ class HipExec : public Executor {
     if (b) HIP_OK(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, stream_));
   }
   // Kernel choice and work items of a launch (host only).
+  // cfg (padded BF16 launches only): 0 the static rule (choose_wave /
+  // choose_tile), 1..3 the tiles 64x64, 64x128, 128x64, 4 the wave kernel.
   Prepared* configure(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc,
-                      std::vector<WorkItem>& items, std::vector<RedItem>& reds) {
+                      std::vector<WorkItem>& items, std::vector<RedItem>& reds, int cfg = 0) {
     auto* P = new Prepared();
     P->da = da;
     P->db = db;
     P->dc = dc;
+    const bool f8 = da == DT_FP8 || db == DT_FP8;
     P->mode = (da == DT_F64) ? DT_F64 : (da == DT_F32 ? DT_F32 : DT_BF16);
     if (P->mode == DT_BF16 && (dc == DT_BF16 || dc == DT_F32)) {
       bool ok = true;
+      // vector loads: 16-byte aligned BF16 rows, 8-byte aligned FP8 rows
+      const uintptr_t ma = da == DT_FP8 ? 7 : 15, mb = db == DT_FP8 ? 7 : 15;
       for (const RawTerm& T : terms) {
         if (T.flags & (TF_IDENT_A | TF_IDENT_B)) continue;
         // the scaled-frame accumulation needs weights whose ratios stay in FP32 range
         const double aw = std::fabs(T.alpha);
-        if (!(T.flags & TF_PAD_A) || !(T.flags & TF_PAD_B) || ((uintptr_t)T.A & 15) || ((uintptr_t)T.B & 15) ||
+        if (!(T.flags & TF_PAD_A) || !(T.flags & TF_PAD_B) || ((uintptr_t)T.A & ma) || ((uintptr_t)T.B & mb) ||
             (T.lda & 7) || (T.ldb & 7) || !(aw >= 1e-12 && aw <= 1e12)) {
           ok = false;
           break;
         }
       }
-      P->padded = ok && !std::getenv("DMRG_NO_PADDED_KERNEL");
+      P->padded = ok && (f8 || !std::getenv("DMRG_NO_PADDED_KERNEL"));
     }
+    if (f8 && !P->padded) {
+      delete P;
+      throw std::runtime_error("executor: FP8 operands need padded, aligned operands and weights within 1e-12..1e12");
+    }
+    if (f8 && cfg == 4) cfg = 1;  // no wave kernel for FP8 operands
     P->kt = P->padded ? 32 : (P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16);
-    if (P->padded) {
-      P->wave = choose_wave(jobs, terms, 32);
+    if (P->padded && cfg > 0) {
+      static const int tiles[4][2] = {{64, 64}, {64, 128}, {128, 64}, {32, 32}};
+      P->wave = cfg == 4;
+      P->bm = tiles[cfg - 1][0];
+      P->bn = tiles[cfg - 1][1];
+    } else if (P->padded) {
+      P->wave = !f8 && choose_wave(jobs, terms, 32);
       if (P->wave) P->bm = P->bn = 32;
       else choose_tile(jobs, terms, P->bm, P->bn);
     } else if (P->mode == DT_F64 && dc == DT_F64 && !std::getenv("DMRG_NO_F64_WAVE")) {
@@ -1922,7 +2020,7 @@ class HipExec : public Executor {
       if (P->wave) P->bm = P->bn = 32;
     }
     try {
-      pick(P->mode, da, db, dc, P->kt);  // validate
+      if (!f8) pick(P->mode, da, db, dc, P->kt);  // validate
       if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
       plan_items(jobs, terms, P->kt, P->bm, P->bn, P->wave ? 65536.0 : 16384.0, 64.0, items, reds, P->nslots);
       P->nitems = (long long)items.size();
@@ -1938,10 +2036,86 @@ class HipExec : public Executor {
     return (size_t)P->nslots * P->bm * P->bn * (P->mode == DT_F64 ? 8 : 4);
   }
   void* prepare(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc) override {
+    return prepare_cfg(jobs, terms, da, db, dc, 0);
+  }
+  // Measured choice of the kernel configuration of a padded BF16 launch:
+  // every candidate (three LDS tiles, the wave kernel) is prepared and timed
+  // on the launch itself (one warm-up and one timed run; the launch's outputs
+  // are scratch that the caller clears or overwrites before real use), and
+  // the fastest kept.  Choices are cached per launch class -- operand and
+  // output types and the log2 buckets of the padded MFMA work, the job count
+  // and the mean m, n and K -- so launches of one shape are timed once per
+  // process; DMRG_TUNE_FILE names a file that keeps the cache across
+  // processes, DMRG_TUNE=0 falls back to the static rule.
+  void* prepare_tuned(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db,
+                      int dc) override {
+    const bool f8 = da == DT_FP8 || db == DT_FP8;
+    if ((da != DT_BF16 && da != DT_FP8) || (db != DT_BF16 && db != DT_FP8) || (dc != DT_BF16 && dc != DT_F32) ||
+        jobs.empty() ||
+        (std::getenv("DMRG_TUNE") && std::atoi(std::getenv("DMRG_TUNE")) == 0) || std::getenv("DMRG_TILE") ||
+        std::getenv("DMRG_WAVE") || std::getenv("DMRG_NO_PADDED_KERNEL"))
+      return prepare(jobs, terms, da, db, dc);
+    const std::string key = tune_key(jobs, terms, dc);
+    std::lock_guard<std::mutex> lock(tune_mu());
+    load_tune_file();
+    auto it = tune_map().find(key);
+    if (it != tune_map().end()) return prepare_cfg(jobs, terms, da, db, dc, it->second);
+    int best = 0;
+    float best_ms = 0.0f;
+    void* keep = nullptr;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    for (int cfg = 1; cfg <= (f8 ? 3 : 4); ++cfg) {
+      void* h = prepare_cfg(jobs, terms, da, db, dc, cfg);
+      if (!((Prepared*)h)->padded) {  // not a padded launch after all: no choice to make
+        HIP_OK(hipEventDestroy(e0));
+        HIP_OK(hipEventDestroy(e1));
+        if (keep) drop(keep);
+        return h;
+      }
+      const bool was = timing_;
+      timing_ = false;
+      run(h);  // warm-up
+      HIP_OK(hipEventRecord(e0, stream_));
+      run(h);
+      HIP_OK(hipEventRecord(e1, stream_));
+      timing_ = was;
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      if (!keep || ms < best_ms) {
+        if (keep) drop(keep);
+        keep = h;
+        best = cfg;
+        best_ms = ms;
+      } else {
+        drop(h);
+      }
+    }
+    HIP_OK(hipEventDestroy(e0));
+    HIP_OK(hipEventDestroy(e1));
+    tune_map()[key] = best;
+    ++tuned_count();
+    save_tune_file(key, best);
+    return keep;
+  }
+  std::string tuner_report() const override {
+    std::lock_guard<std::mutex> lock(tune_mu());
+    int cnt[5] = {0, 0, 0, 0, 0};
+    for (auto& kv : tune_map()) cnt[std::max(0, std::min(4, kv.second))]++;
+    char b[256];
+    std::snprintf(b, sizeof b,
+                  "{\"classes\": %zu, \"timed_here\": %d, \"64x64\": %d, \"64x128\": %d, \"128x64\": %d, \"wave32x32\": %d}",
+                  tune_map().size(), tuned_count(), cnt[1], cnt[2], cnt[3], cnt[4]);
+    return b;
+  }
+  void* prepare_cfg(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc,
+                    int cfg) {
     Scope sc(t_prep_);
     std::vector<WorkItem> items;
     std::vector<RedItem> reds;
-    Prepared* P = configure(jobs, terms, da, db, dc, items, reds);
+    Prepared* P = configure(jobs, terms, da, db, dc, items, reds, cfg);
     if (P->nitems) {
       P->d_jobs = (RawJob*)alloc(jobs.size() * sizeof(RawJob));
       P->d_terms = (RawTerm*)alloc(std::max<size_t>(terms.size(), 1) * sizeof(RawTerm));
@@ -1988,7 +2162,8 @@ class HipExec : public Executor {
                            P->d_items + t0, P->part ? P->part : part_, nt);
       }
     } else {
-      KernelFn k = P->padded ? pick_padded(P->dc, P->bm, P->bn) : pick(P->mode, P->da, P->db, P->dc, P->kt);
+      KernelFn k = P->padded ? pick_padded(P->dc, P->bm, P->bn, P->da == DT_FP8, P->db == DT_FP8)
+                             : pick(P->mode, P->da, P->db, P->dc, P->kt);
       for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
         const long long nt = std::min(maxg, P->nitems - t0);
         hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0,
@@ -2103,14 +2278,51 @@ class HipExec : public Executor {
     else throw std::runtime_error("executor: unsupported pack dtype");
     HIP_OK(hipGetLastError());
   }
-  void gather(double* dst, const void* src, int ds, const int* idx, size_t n, double a, const double* x) override {
+  void gather(double* dst, const void* src, int ds, const int* idx, size_t n, double a, const double* x,
+              const double* mul) override {
     if (!n) return;
     const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
     const long long nn = (long long)n;
-    if (ds == DT_F64) hipLaunchKernelGGL((gather_kernel<DT_F64>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x);
-    else if (ds == DT_F32) hipLaunchKernelGGL((gather_kernel<DT_F32>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x);
-    else if (ds == DT_BF16) hipLaunchKernelGGL((gather_kernel<DT_BF16>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x);
+    if (ds == DT_F64) hipLaunchKernelGGL((gather_kernel<DT_F64>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x, mul);
+    else if (ds == DT_F32) hipLaunchKernelGGL((gather_kernel<DT_F32>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x, mul);
+    else if (ds == DT_BF16) hipLaunchKernelGGL((gather_kernel<DT_BF16>), dim3(grid), dim3(256), 0, stream_, dst, src, idx, nn, a, x, mul);
     else throw std::runtime_error("executor: unsupported gather dtype");
+    HIP_OK(hipGetLastError());
+  }
+  void fp8_scales(const double* src, int64_t nseg, int64_t seg, double* d_scale) override {
+    if (nseg <= 0) return;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(64, (seg + 255) / 256));
+    double* part = (double*)alloc((size_t)nseg * nb * sizeof(double));
+    for (int64_t y0 = 0; y0 < nseg; y0 += 65535) {
+      const int ny = (int)std::min<int64_t>(65535, nseg - y0);
+      hipLaunchKernelGGL(absmax_partial, dim3(nb, ny), dim3(256), 0, stream_, src + y0 * seg, (long long)seg,
+                         (long long)seg, part + y0 * nb);
+    }
+    hipLaunchKernelGGL(pow2_scale, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, stream_, part, nb, (int)nseg,
+                       d_scale);
+    HIP_OK(hipGetLastError());
+    sync();
+    release(part);
+  }
+  void to_fp8(void* dst, const double* src, int64_t n, int64_t seg, const double* d_scale) override {
+    if (n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(to_fp8_kernel, dim3(grid), dim3(256), 0, stream_, (unsigned char*)dst, src, (long long)n,
+                       (long long)seg, d_scale);
+    HIP_OK(hipGetLastError());
+  }
+  void pack_fp8(void* dst, const double* src, const int* idx, size_t n, double* d_scale, const double* src_all,
+                size_t n_all) override {
+    if (!n) return;
+    // scale of the whole source vector (one segment), then the packed copy
+    const int nb = (int)std::max<size_t>(1, std::min<size_t>(1024, (n_all + 255) / 256));
+    if (!fp8_part_) fp8_part_ = (double*)alloc(1024 * sizeof(double));
+    hipLaunchKernelGGL(absmax_partial, dim3(nb, 1), dim3(256), 0, stream_, src_all, (long long)n_all, (long long)n_all,
+                       fp8_part_);
+    hipLaunchKernelGGL(pow2_scale, dim3(1), dim3(1), 0, stream_, fp8_part_, nb, 1, d_scale);
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(pack_fp8_kernel, dim3(grid), dim3(256), 0, stream_, (unsigned char*)dst, src, idx, (long long)n,
+                       d_scale);
     HIP_OK(hipGetLastError());
   }
   void shifted_copy_at(void* dst, int dd, const double* src, const int* idx, size_t n, double a) override {
@@ -2253,6 +2465,63 @@ class HipExec : public Executor {
   hipStream_t stream() const { return stream_; }
 
  private:
+  // ---- tile autotuner state (prepare_tuned), shared by every executor of
+  // the process so that contexts with the same launches make the same choice
+  static std::mutex& tune_mu() {
+    static std::mutex m;
+    return m;
+  }
+  static std::map<std::string, int>& tune_map() {  // launch class -> configuration
+    static std::map<std::string, int> m;
+    return m;
+  }
+  static int& tuned_count() {  // classes timed in this process
+    static int n = 0;
+    return n;
+  }
+  static std::string tune_key(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int dc) {
+    double work = 0.0, sm = 0.0, sn = 0.0, sk = 0.0, nk = 0.0;
+    for (const RawJob& J : jobs) {
+      sm += J.m;
+      sn += J.n;
+      double kp = 0.0;
+      for (int64_t t = J.tbeg; t < J.tend; ++t)
+        if (!(terms[t].flags & (TF_IDENT_A | TF_IDENT_B))) {
+          kp += (double)((terms[t].k + 31) / 32 * 32);
+          sk += terms[t].k;
+          nk += 1.0;
+        }
+      work += (double)((J.m + 63) / 64) * (double)((J.n + 63) / 64) * 4096.0 * kp;
+    }
+    const double nj = (double)jobs.size();
+    auto b2 = [](double x) { return (int)std::lround(std::log2(std::max(x, 1.0))); };
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "dc%d_w%d_j%d_m%d_n%d_k%d", dc, b2(work), b2(nj), b2(sm / nj), b2(sn / nj),
+                  b2(nk > 0 ? sk / nk : 1.0));
+    return buf;
+  }
+  static void load_tune_file() {
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char* f = std::getenv("DMRG_TUNE_FILE");
+    if (!f) return;
+    FILE* fp = std::fopen(f, "r");
+    if (!fp) return;
+    char key[128];
+    int cfg = 0;
+    while (std::fscanf(fp, "%127s %d", key, &cfg) == 2)
+      if (cfg >= 1 && cfg <= 4) tune_map()[key] = cfg;
+    std::fclose(fp);
+  }
+  static void save_tune_file(const std::string& key, int cfg) {
+    const char* f = std::getenv("DMRG_TUNE_FILE");
+    if (!f) return;
+    FILE* fp = std::fopen(f, "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s %d\n", key.c_str(), cfg);
+    std::fclose(fp);
+  }
   // Offsets of a fixed-scratch launch's task lists from base (256-byte
   // aligned pieces); sets the device pointers if base is given.  Returns the
   // bytes they span.
@@ -2290,6 +2559,7 @@ class HipExec : public Executor {
   void* part_ = nullptr;  // partial tiles of split items, shared by all launches
   size_t part_bytes_ = 0;
   double* dot_part_ = nullptr;
+  double* fp8_part_ = nullptr;  // partial maxima of pack_fp8
   double* dot_out_ = nullptr;
   hipStream_t stream_ = nullptr;
   bool timing_ = false;

@@ -144,6 +144,8 @@ void Context::free_buf(int id) {
       b.p[d] = nullptr;
     }
   b.n = 0;
+  b.fp8_seg = 0;
+  b.fp8_scale.clear();
 }
 
 void Context::ensure_dtype(int id, int dt) {
@@ -154,6 +156,27 @@ void Context::ensure_dtype(int id, int dt) {
   bytes_in_use += b.n * (int64_t)dtype_size(dt);
   peak_bytes = std::max(peak_bytes, bytes_in_use);
   ex->convert(b.p[dt], dt, b.p[DT_F64], DT_F64, (size_t)b.n);
+}
+
+void Context::ensure_fp8(int id, int64_t seg, const double* src) {
+  DevBuf& b = bufs[id];
+  if (b.p[DT_FP8] || b.n == 0) return;
+  if (seg <= 0 || b.n % seg) throw std::runtime_error("ensure_fp8: segment does not divide the buffer");
+  const int64_t nseg = b.n / seg;
+  charge(b.n);
+  double* d_scale = (double*)ex->alloc((size_t)nseg * 2 * sizeof(double));
+  if (!src) src = (const double*)b.p[DT_F64];
+  ex->fp8_scales(src, nseg, seg, d_scale);
+  b.p[DT_FP8] = ex->alloc((size_t)b.n);
+  bytes_in_use += b.n;
+  peak_bytes = std::max(peak_bytes, bytes_in_use);
+  ex->to_fp8(b.p[DT_FP8], src, b.n, seg, d_scale);
+  std::vector<double> sc((size_t)nseg * 2);
+  ex->download(sc.data(), d_scale, sc.size() * sizeof(double));
+  ex->release(d_scale);
+  b.fp8_seg = seg;
+  b.fp8_scale.resize((size_t)nseg);
+  for (int64_t i = 0; i < nseg; ++i) b.fp8_scale[(size_t)i] = sc[(size_t)(2 * i)];
 }
 
 void Context::alloc_dtype(int id, int dt) {
@@ -621,6 +644,15 @@ void Context::resolve(const GemmBatch& b, std::vector<RawJob>& jobs, std::vector
     if (!base) throw std::runtime_error("resolve: buffer missing in requested precision");
     return base + r.off * (int64_t)dtype_size(dt);
   };
+  // scale of an FP8 operand (1 for other types and unscaled buffers)
+  auto S = [&](const BufRef& r, int dt) -> double {
+    if (dt != DT_FP8) return 1.0;
+    int id = r.buf;
+    if (id < 0) id = (-id < 8) ? ph[-id] : -1;
+    const DevBuf& b = bufs[id];
+    if (b.fp8_seg <= 0) return 1.0;
+    return b.fp8_scale[(size_t)(r.off / b.fp8_seg)];
+  };
   jobs.resize(b.jobs.size());
   terms.resize(b.terms.size());
   for (size_t i = 0; i < b.jobs.size(); ++i) {
@@ -629,8 +661,9 @@ void Context::resolve(const GemmBatch& b, std::vector<RawJob>& jobs, std::vector
   }
   for (size_t i = 0; i < b.terms.size(); ++i) {
     const GemmTerm& t = b.terms[i];
-    terms[i] = RawTerm{(t.flags & TF_IDENT_A) ? nullptr : P(t.A, dta), (t.flags & TF_IDENT_B) ? nullptr : P(t.B, dtb),
-                       t.lda, t.ldb, t.k, t.flags, t.alpha};
+    const bool ia = t.flags & TF_IDENT_A, ib = t.flags & TF_IDENT_B;
+    terms[i] = RawTerm{ia ? nullptr : P(t.A, dta), ib ? nullptr : P(t.B, dtb), t.lda, t.ldb, t.k, t.flags,
+                       t.alpha * (ia ? 1.0 : S(t.A, dta)) * (ib ? 1.0 : S(t.B, dtb))};
   }
 }
 

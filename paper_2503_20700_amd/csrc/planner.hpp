@@ -103,6 +103,10 @@ struct DevBuf {
   int64_t n = 0;       // elements
   void* p[4] = {nullptr, nullptr, nullptr, nullptr};  // per dtype copy
   bool view = false;   // points into memory the buffer does not own
+  // FP8 copy: one power-of-two scale per segment of fp8_seg elements (one
+  // operator of a family); the stored values are x / scale
+  int64_t fp8_seg = 0;
+  std::vector<double> fp8_scale;
 };
 
 class Context;
@@ -247,6 +251,9 @@ class Context {
   void* ptr(int buf, int dt = DT_F64) const { return bufs[buf].p[dt]; }
   void ensure_dtype(int buf, int dt);  // create converted copy from the F64 master
   void alloc_dtype(int buf, int dt);   // storage in dtype dt, contents undefined
+  // FP8 copy of buf with one scale per segment of seg elements, converted
+  // from src (default: the buffer's FP64 master)
+  void ensure_fp8(int buf, int64_t seg, const double* src = nullptr);
   int view_buf();                      // entry that points into memory it does not own
   void set_view(int buf, int dt, void* p, int64_t n);
   int ph[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // placeholder buffers (-1..-7) of the current plan

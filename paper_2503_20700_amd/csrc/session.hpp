@@ -34,6 +34,7 @@ struct dmrg_ctx {
   int b_in = -1, b_out = -1, b_x = -1, b_ones = -1, b_diag = -1, b_inp = -1, b_outp = -1;
   void* d_pidx = nullptr;  // padded psi index -> caller index (int32, -1 = padding)
   void* d_uidx = nullptr;  // caller index -> index in b_outp (int32)
+  double* d_pscale = nullptr;  // (s, 1/s) of the FP8 copy of psi_in
   long long plan_serial = 0;  // bumped whenever a new H*psi plan is made
   // start vector carried by the last truncation to the block it moved to
   std::vector<double> guess;
@@ -48,7 +49,7 @@ struct dmrg_ctx {
     void* graph = nullptr;     // recorded H*psi sequence (opts.hpsi_graph)
     long long graph_gen = -1;  // executor scratch generation it was recorded at
   };
-  Prepared prep[3];
+  Prepared prep[4];
   // cut spectrum of the last truncation
   std::vector<double> cut_values;
   std::vector<int> cut_spins;
@@ -91,6 +92,8 @@ struct dmrg_ctx {
       d_pidx = nullptr;
       if (d_uidx) ex->release(d_uidx);
       d_uidx = nullptr;
+      if (d_pscale) ex->release(d_pscale);
+      d_pscale = nullptr;
       if (C->Lblk) {
         for (auto& t : C->Lblk->tmp) C->free_buf(t.buf);
         C->Lblk->tmp.clear();
@@ -129,6 +132,7 @@ struct dmrg_ctx {
       const std::vector<int> m = plan->lay.pack_map();
       d_pidx = ex->alloc(std::max<size_t>(m.size(), 1) * sizeof(int));
       if (!m.empty()) ex->upload(d_pidx, m.data(), m.size() * sizeof(int));
+      d_pscale = (double*)ex->alloc(2 * sizeof(double));
       const std::vector<int> u = plan->lay.unpack_map();
       d_uidx = ex->alloc(std::max<size_t>(u.size(), 1) * sizeof(int));
       if (!u.empty()) ex->upload(d_uidx, u.data(), u.size() * sizeof(int));
@@ -143,49 +147,66 @@ struct dmrg_ctx {
     C->run_batch(plan->diag);
   }
 
-  static int op_dt(int prec) { return prec == DMRG_FP64 ? dmrg::DT_F64 : prec == DMRG_FP32 ? dmrg::DT_F32 : dmrg::DT_BF16; }
+  // storage of the operator blocks and of psi, of the X intermediates, and of
+  // the psi' accumulator for each precision (FP8 operands give BF16 X)
+  static int op_dt(int prec) {
+    return prec == DMRG_FP64 ? dmrg::DT_F64 : prec == DMRG_FP32 ? dmrg::DT_F32 : prec == DMRG_FP8 ? dmrg::DT_FP8 : dmrg::DT_BF16;
+  }
+  static int x_dt(int prec) { return prec == DMRG_FP8 ? dmrg::DT_BF16 : op_dt(prec); }
   static int out_dt(int prec) { return prec == DMRG_FP64 ? dmrg::DT_F64 : dmrg::DT_F32; }
+  // copy of an operator family buffer in storage type od (FP8: one scale per operator)
+  void family_copy(const dmrg::Family& F, int od, const double* src = nullptr) {
+    if (F.buf < 0) return;
+    if (od == dmrg::DT_FP8) C->ensure_fp8(F.buf, std::max<int64_t>(F.lay->size, 1), src);
+    else C->ensure_dtype(F.buf, od);
+  }
 
   // The low-precision copy of a block's Hamiltonian: H - sigma * 1 with sigma
-  // the mean of its FP64 diagonal (Block::h_shift).
+  // the mean of its FP64 diagonal (Block::h_shift, set when the first copy
+  // is made; every copy of the block uses it).
   void shifted_h_copy(dmrg::Block* blk, int od) {
     dmrg::Family& F = blk->fam[dmrg::F_H];
-    if (F.buf < 0 || C->ptr(F.buf, od) || F.nops < 1) {
-      if (F.buf >= 0) C->ensure_dtype(F.buf, od);
+    if (F.buf < 0 || C->ptr(F.buf, od) || F.nops < 1 || C->bufs[F.buf].n == 0) {
+      family_copy(F, od);
       return;
     }
-    C->ensure_dtype(F.buf, od);
     std::vector<int> diag;
-    for (const auto& b : F.lay->blocks) {
-      if (b.bra != b.ket) continue;
-      const int d = blk->bond.secs[b.bra].dim;
-      for (int i = 0; i < d; ++i) diag.push_back((int)(b.off + (int64_t)i * b.ld + i));
+    for (const auto& b : F.lay->blocks)
+      if (b.bra == b.ket)
+        for (int i = 0; i < blk->bond.secs[b.bra].dim; ++i) diag.push_back((int)(b.off + (int64_t)i * b.ld + i));
+    if (diag.empty()) {
+      family_copy(F, od);
+      return;
     }
-    if (diag.empty()) return;
+    void* di = ex->alloc(diag.size() * sizeof(int));
+    ex->upload(di, diag.data(), diag.size() * sizeof(int));
+    const double* h64 = (const double*)C->ptr(F.buf);
     if (!blk->h_shift_set) {
-      void* di = ex->alloc(diag.size() * sizeof(int));
       double* dv = (double*)ex->alloc(diag.size() * 8);
-      ex->upload(di, diag.data(), diag.size() * sizeof(int));
-      ex->gather(dv, C->ptr(F.buf), dmrg::DT_F64, (const int*)di, diag.size());
+      ex->gather(dv, h64, dmrg::DT_F64, (const int*)di, diag.size());
       std::vector<double> v(diag.size());
       ex->download(v.data(), dv, v.size() * 8);
-      double s = 0.0;
-      for (double x : v) s += x;
-      blk->h_shift = s / (double)v.size();
-      blk->h_shift_set = true;
       ex->release(dv);
-      ex->shifted_copy_at(C->ptr(F.buf, od), od, (const double*)C->ptr(F.buf), (const int*)di, diag.size(),
-                          -blk->h_shift);
-      ex->sync();
-      ex->release(di);
-    } else {
-      void* di = ex->alloc(diag.size() * sizeof(int));
-      ex->upload(di, diag.data(), diag.size() * sizeof(int));
-      ex->shifted_copy_at(C->ptr(F.buf, od), od, (const double*)C->ptr(F.buf), (const int*)di, diag.size(),
-                          -blk->h_shift);
-      ex->sync();
-      ex->release(di);
+      double sum = 0.0;
+      for (double x : v) sum += x;
+      blk->h_shift = sum / (double)v.size();
+      blk->h_shift_set = true;
     }
+    if (od == dmrg::DT_FP8) {
+      // FP8: convert a shifted FP64 copy, so that the scale fits H - sigma
+      const int64_t n = C->bufs[F.buf].n;
+      double* tmp = (double*)ex->alloc((size_t)n * 8);
+      ex->copy_d2d(tmp, h64, (size_t)n * 8);
+      ex->shifted_copy_at(tmp, dmrg::DT_F64, h64, (const int*)di, diag.size(), -blk->h_shift);
+      family_copy(F, od, tmp);
+      ex->sync();
+      ex->release(tmp);
+    } else {
+      C->ensure_dtype(F.buf, od);
+      ex->shifted_copy_at(C->ptr(F.buf, od), od, h64, (const int*)di, diag.size(), -blk->h_shift);
+      ex->sync();
+    }
+    ex->release(di);
   }
 
   // What the low-precision H*psi leaves out and end_hpsi adds back in FP64:
@@ -202,19 +223,16 @@ struct dmrg_ctx {
 
   // Operator families and plan buffers in the storage type of precision prec.
   void ready_dtypes(int prec) {
-    const int od = op_dt(prec), xd = op_dt(prec), outd = out_dt(prec);
+    const int od = op_dt(prec), xd = x_dt(prec), outd = out_dt(prec);
     if (od != dmrg::DT_F64) {
       for (dmrg::Block* blk : {C->Lblk.get(), C->Rblk.get()}) {
         shifted_h_copy(blk, od);
         if (std::getenv("DMRG_VERBOSE"))
           std::fprintf(stderr, "[dmrg] %s block Hamiltonian shift %.6f (%s)\n", blk->left ? "left" : "right",
                        blk->h_shift, blk->h_shift_set ? "set" : "unset");
-        for (int f = 0; f < dmrg::kNumFam; ++f)
-          if (blk->fam[f].buf >= 0) C->ensure_dtype(blk->fam[f].buf, od);
-        for (auto& t : blk->tmp)
-          if (t.buf >= 0) C->ensure_dtype(t.buf, od);
+        for (int f = 0; f < dmrg::kNumFam; ++f) family_copy(blk->fam[f], od);
+        for (auto& t : blk->tmp) family_copy(t, od);
       }
-      C->alloc_dtype(b_in, od);
       C->alloc_dtype(b_inp, od);
       C->alloc_dtype(b_x, xd);
       C->alloc_dtype(b_outp, outd);
@@ -224,16 +242,16 @@ struct dmrg_ctx {
   void prepare(int prec) {
     Prepared& P = prep[prec];
     if (P.ready) return;
-    const int od = op_dt(prec), xd = op_dt(prec), outd = out_dt(prec);
+    const int od = op_dt(prec), xd = x_dt(prec), outd = out_dt(prec);
     ready_dtypes(prec);
     bind();
     for (auto& ch : plan->chunks) {
       std::vector<dmrg::RawJob> j;
       std::vector<dmrg::RawTerm> t;
       C->resolve(ch.stageL, j, t, od, od, xd);
-      P.L.push_back(ex->prepare(j, t, od, od, xd));
+      P.L.push_back(ex->prepare_tuned(j, t, od, od, xd));
       C->resolve(ch.stageR, j, t, xd, od, outd);
-      P.R.push_back(ex->prepare(j, t, xd, od, outd));
+      P.R.push_back(ex->prepare_tuned(j, t, xd, od, outd));
     }
     P.ready = true;
   }
@@ -242,16 +260,19 @@ struct dmrg_ctx {
   // b_in and a cleared accumulator b_outp.
   void begin_hpsi(dmrg::Executor* e, int prec) {
     const int od = op_dt(prec), outd = out_dt(prec);
-    e->pack(C->ptr(b_inp, od), od, (const double*)C->ptr(b_in), (const int*)d_pidx, (size_t)plan->lay.psize);
+    if (od == dmrg::DT_FP8)  // psi / s with s a power of two from max|psi| (d_pscale)
+      e->pack_fp8(C->ptr(b_inp, od), (const double*)C->ptr(b_in), (const int*)d_pidx, (size_t)plan->lay.psize, d_pscale,
+                  (const double*)C->ptr(b_in), (size_t)plan->lay.size);
+    else
+      e->pack(C->ptr(b_inp, od), od, (const double*)C->ptr(b_in), (const int*)d_pidx, (size_t)plan->lay.psize);
     e->zero(C->ptr(b_outp, outd), (size_t)plan->lay.size * dmrg::dtype_size(outd));
   }
   // After them: b_out (FP64, caller layout) from b_outp.
   void end_hpsi(dmrg::Executor* e, int prec) {
     const int outd = out_dt(prec);
     const double sh = prec == DMRG_FP64 ? 0.0 : lo_shift();
-    if (std::getenv("DMRG_VERBOSE")) std::fprintf(stderr, "[dmrg] low-precision shift added back: %.6f\n", sh);
     e->gather((double*)C->ptr(b_out), C->ptr(b_outp, outd), outd, (const int*)d_uidx, (size_t)plan->lay.size, sh,
-              sh != 0.0 ? (const double*)C->ptr(b_in) : nullptr);
+              sh != 0.0 ? (const double*)C->ptr(b_in) : nullptr, prec == DMRG_FP8 ? d_pscale : nullptr);
   }
 
   // The launches of psi_out = H psi_in on b_in / b_out (prepared already).

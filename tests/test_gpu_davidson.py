@@ -84,3 +84,25 @@ def test_davidson_with_hpsi_graph_equals_eager():
     assert a["converged"] and b["converged"]
     assert a["energy"] == b["energy"] and (a["n_lo"], a["n_fp64"]) == (b["n_lo"], b["n_fp64"])
     assert np.array_equal(a["psi"], b["psi"])
+
+
+def test_fp8_davidson_with_fp64_refinement_reaches_the_fp64_energy():
+    """FP8-operand bulk matvecs, then FP64 refinement from the FP8 phase's
+    Ritz vectors: the residual 1e-7 and the dense eigenvalue to 1e-6 Eh."""
+    from oracle import heff
+    from paper_2503_20700_amd.binding import DMRG
+    from synth.integrals import small_cas
+    from synth.mps import random_mps, random_psi
+    n, ne, ts, d, k, seed = 8, 8, 0, 64, 3, 0
+    print("[davidson fp8]", flush=True)
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    e_ref = np.linalg.eigvalsh(heff.HeffDefinition(h, g, mps, lay).dense())[0]
+    dm = DMRG(h, g, ne, ts, hpsi_prec=3, davidson_max_iter=300)
+    bs, cnt = mps.bond_table()
+    dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+    r = dm.davidson(psi)
+    assert r["converged"] and r["resid"] <= 1e-7
+    assert r["n_lo"] > 0 and r["n_fp64"] > 0
+    assert abs(r["energy"] - e_ref) <= 1e-6

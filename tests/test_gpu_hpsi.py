@@ -248,8 +248,8 @@ EDGE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec,bound", [(0, 1e-10), (1, 2.0 ** -24 * 64), (2, 2.0 ** -8 * 8)],
-                         ids=["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("prec,bound", [(0, 1e-10), (1, 2.0 ** -24 * 64), (2, 2.0 ** -8 * 8), (3, 2.0 ** -4 * 2)],
+                         ids=["fp64", "fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("case", EDGE_CASES, ids=[f"n{c[0]}N{c[1]}S{c[2]}k{c[4]}" for c in EDGE_CASES])
 def test_hpsi_edge_cases_match_oracle(case, prec, bound):
     print(f"[hpsi edge] case={case} prec={prec}", flush=True)
@@ -258,3 +258,18 @@ def test_hpsi_edge_cases_match_oracle(case, prec, bound):
     ref = heff.hpsi(h, g, mps, lay, psi)
     assert np.all(np.isfinite(y))
     assert np.abs(y - ref).max() <= bound * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}N{c[1]}S{c[2]}D{c[3]}" for c in CASES])
+def test_hpsi_fp8_error_bound(case):
+    """FP8 operands (OCP E4M3, unit roundoff 2^-4) with BF16 intermediates:
+    max-norm error against the oracle within 2 * 2^-4 of the largest element."""
+    print(f"[hpsi fp8] case={case}", flush=True)
+    h, g, mps, psi, lay, dm = _setup(*case)
+    y8, _ = dm.hpsi(psi, 3)
+    ref = heff.hpsi(h, g, mps, lay, psi)
+    rel = np.abs(y8 - ref).max() / np.abs(ref).max()
+    assert np.all(np.isfinite(y8))
+    assert 0.0 < rel < 2.0 ** -4 * 2, rel
+    # the Rayleigh quotient within the same relative bound
+    assert abs(psi @ y8 - psi @ ref) <= 2.0 ** -4 * 2 * abs(psi @ ref)

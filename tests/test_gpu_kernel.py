@@ -139,3 +139,53 @@ def test_gemm_bf16_wave_kernel(m, n, k, ta, tb, beta, monkeypatch):
     bound = (2 * 2.0 ** -8 + k * 2.0 ** -24) * 0.625 * (np.abs(a) @ np.abs(b)) + 2.0 ** -24 * np.abs(ref)
     assert np.all(np.isfinite(got))
     assert np.all(np.abs(got - ref) <= 4 * bound + 1e-30)
+
+
+def _e4m3_values():
+    """All finite non-negative OCP E4M3 values (bias 7, subnormals m * 2^-9, max 448)."""
+    vals = []
+    for e in range(16):
+        for m in range(8):
+            if e == 15 and m == 7:
+                continue  # NaN
+            vals.append(m * 2.0 ** -9 if e == 0 else (1 + m / 8) * 2.0 ** (e - 7))
+    return np.array(sorted(set(vals)))
+
+
+def _quantize_e4m3(x):
+    """Round to the nearest E4M3 value, ties to the even code, saturating at 448."""
+    grid = _e4m3_values()
+    codes = {v: i for i, v in enumerate(grid)}  # in increasing order, code parity = mantissa parity
+    out = np.empty_like(x)
+    for i, v in enumerate(np.asarray(x, dtype=np.float32).astype(np.float64).ravel()):
+        a = min(abs(v), 448.0)
+        j = np.searchsorted(grid, a)
+        cand = [grid[max(j - 1, 0)], grid[min(j, len(grid) - 1)]]
+        d0, d1 = abs(a - cand[0]), abs(a - cand[1])
+        q = cand[0] if d0 < d1 else cand[1] if d1 < d0 else (cand[0] if codes[cand[0]] % 2 == 0 else cand[1])
+        out.ravel()[i] = np.copysign(q, v)
+    return out
+
+
+@pytest.mark.parametrize("m,n", [(65, 63), (130, 7)])
+def test_gemm_fp8_operands_are_ocp_e4m3(m, n):
+    """FP8 operands: x / s rounded to OCP E4M3 (nearest, ties to even,
+    saturating), s the smallest power of two with max|x| / s <= 448, widened
+    exactly for the BF16 MFMA.  A times the identity (stored in FP8 too)
+    returns s * E4M3(A / s) exactly."""
+    from paper_2503_20700_amd.binding import gemm_selftest
+    rng = np.random.default_rng(11)
+    a = rng.normal(size=(m, n)) * np.exp(rng.uniform(-6, 6, size=(m, n)))
+    a[0, 0] = 0.0
+    eye = np.eye(n)
+    got = gemm_selftest(a, eye, prec=3, pad_a=True, pad_b=True)
+    s = 2.0 ** np.ceil(np.log2(np.abs(a).max() / 448.0))
+    assert np.abs(a).max() / s <= 448.0 < 2 * np.abs(a).max() / s
+    want = s * _quantize_e4m3(a / s)
+    assert np.array_equal(got, want)
+    # a product: operand rounding 2^-4 each, FP32 accumulation
+    b = rng.normal(size=(n, 40))
+    got = gemm_selftest(a, b, prec=3, pad_a=True, pad_b=True)
+    ref = a @ b
+    bound = (2 * 2.0 ** -4 + n * 2.0 ** -24) * (np.abs(a) @ np.abs(b))
+    assert np.all(np.abs(got - ref) <= 2 * bound + 1e-300)
