@@ -221,6 +221,7 @@ def main():
                     help="cas82_d4096 (default), cas32_d1024, cas8_d64, or batch48")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dmrg-step", action="store_true", help="skip the timed Davidson + truncation step")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8-operand H*psi timing")
     ap.add_argument("--compare-from-random", action="store_true",
                     help="converged step: run the FP64 solve from the random start too (solver-level speedup)")
     ap.add_argument("--accuracy-small", action="store_true",
@@ -250,7 +251,7 @@ def main():
         return
 
     import torch
-    from paper_2503_20700_amd.binding import BF16, DMRG, FP64
+    from paper_2503_20700_amd.binding import BF16, DMRG, FP8, FP64
     from synth.mps import random_mps, random_psi
 
     dev = torch.device("cuda:0")
@@ -324,6 +325,27 @@ def main():
     ylo_h, yhi_h = ylo.cpu().numpy(), yhi.cpu().numpy()
     rel = float(np.abs(ylo_h - yhi_h).max() / np.abs(yhi_h).max())
     e_lo, e_hi = float(psi @ ylo_h), float(psi @ yhi_h)
+    # FP8 operands (E4M3): the same product, timed outside the steps (not in
+    # the profiler runs, whose summaries take the last BF16 H*psi)
+    fp8 = None
+    if not args.no_fp8:
+        y8 = torch.empty_like(x)
+        hpsi(FP8, y8)  # prepares (and tunes) the FP8 launches
+        t8 = k8 = 0.0
+        reps8 = max(1, min(args.steps, 3))
+        for _ in range(reps8):
+            dm.kernel_timing(1)
+            t0 = time.perf_counter()
+            hpsi(FP8, y8)
+            t8 += time.perf_counter() - t0
+            ms, _ = dm.kernel_timing(0)
+            k8 += ms
+        y8_h = y8.cpu().numpy()
+        fp8 = {"ms_per_hpsi": t8 / reps8 * 1e3, "kernel_ms_per_hpsi": k8 / reps8,
+               "kernel_tflops": flops / (k8 / reps8 * 1e-3) / 1e12, "reps": reps8,
+               "rel_err_vs_fp64": float(np.abs(y8_h - yhi.cpu().numpy()).max() / np.abs(yhi.cpu().numpy()).max()),
+               "storage": "operators and psi in OCP E4M3 (power-of-two scales), X in BF16, BF16 MFMA, FP32 accumulation"}
+        log(f"FP8 H*psi: {fp8['ms_per_hpsi']:.1f} ms, rel err vs FP64 {fp8['rel_err_vs_fp64']:.2e}")
     # full-size property checks (FP64): reproducibility and Hermiticity <phi|H psi> = <H phi|psi>
     phi = np.random.default_rng(7).normal(size=psi.size)
     hphi, _ = dm.hpsi(phi, FP64)
@@ -375,9 +397,11 @@ def main():
         "traffic_detail": traffic_detail,
         "cpu_baseline": base,
         "hpsi_flops": flops,
+        "hpsi_flops_executed": st["hpsi_flops_executed"],
         "bf16": {"ms_per_hpsi": t_lo / K * 1e3, "kernel_ms_per_hpsi": k_lo / K, "launches_per_hpsi": n_lo // K},
         "fp64": {"tflops": hi_tflops, "kernel_tflops": hi_kernel_tflops, "roofline_frac": hi_kernel_tflops / PEAK["f64"],
                  "ms_per_hpsi": t_hi / K * 1e3, "kernel_ms_per_hpsi": k_hi / K},
+        "fp8": fp8,
         "speedup_bf16_vs_fp64": t_hi / t_lo if t_lo > 0 else None,
         "rel_err_bf16_vs_fp64": rel,
         "rayleigh_bf16_minus_fp64_Eh": e_lo - e_hi,

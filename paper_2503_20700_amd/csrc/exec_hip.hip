@@ -1215,13 +1215,17 @@ __global__ __launch_bounds__(256) void absmax_partial(const double* __restrict__
 }
 
 // scale[y] = (s, 1/s) of segment y from its gridDim-wide partial maxima
-__global__ void pow2_scale(const double* __restrict__ part, int nb, int nseg, double* __restrict__ scale) {
+// Segments whose largest magnitude is at most `floor` keep the scale 1 (their
+// elements then round to E4M3 as they are, which flushes values far below
+// its smallest subnormal 2^-9 to zero).
+__global__ void pow2_scale(const double* __restrict__ part, int nb, int nseg, double* __restrict__ scale,
+                           double floor) {
   const int y = blockIdx.x * blockDim.x + threadIdx.x;
   if (y >= nseg) return;
   double m = 0.0;
   for (int i = 0; i < nb; ++i) m = fmax(m, part[(long long)y * nb + i]);
   int e = 0;
-  if (m > 0.0) {
+  if (m > floor) {
     (void)frexp(m / 448.0, &e);  // m / 448 = f * 2^e, f in [0.5, 1): m / 2^e <= 448
   }
   scale[2 * y] = ldexp(1.0, e);
@@ -1988,21 +1992,30 @@ class HipExec : public Executor {
       bool ok = true;
       // vector loads: 16-byte aligned BF16 rows, 8-byte aligned FP8 rows
       const uintptr_t ma = da == DT_FP8 ? 7 : 15, mb = db == DT_FP8 ? 7 : 15;
+      double wmin = HUGE_VAL, wmax = 0.0;
       for (const RawTerm& T : terms) {
         if (T.flags & (TF_IDENT_A | TF_IDENT_B)) continue;
-        // the scaled-frame accumulation needs weights whose ratios stay in FP32 range
         const double aw = std::fabs(T.alpha);
         if (!(T.flags & TF_PAD_A) || !(T.flags & TF_PAD_B) || ((uintptr_t)T.A & ma) || ((uintptr_t)T.B & mb) ||
-            (T.lda & 7) || (T.ldb & 7) || !(aw >= 1e-12 && aw <= 1e12)) {
+            (T.lda & 7) || (T.ldb & 7) || !(aw >= 1e-30 && aw <= 1e30)) {
           ok = false;
           break;
         }
+        wmin = std::min(wmin, aw);
+        wmax = std::max(wmax, aw);
       }
+      // The scaled-frame accumulation divides the running sum by the weight
+      // in flight and multiplies it by weight ratios, in FP32: weights within
+      // 1e-30..1e30 and ratios up to 1e30 keep both far inside FP32 range
+      // (the FP8 scales of the operands are folded into the weights, which
+      // makes them small).
+      if (ok && wmax > 0.0 && wmax > 1e30 * wmin) ok = false;
       P->padded = ok && (f8 || !std::getenv("DMRG_NO_PADDED_KERNEL"));
     }
     if (f8 && !P->padded) {
       delete P;
-      throw std::runtime_error("executor: FP8 operands need padded, aligned operands and weights within 1e-12..1e12");
+      throw std::runtime_error(
+          "executor: FP8 operands need padded, aligned operands and weights within 1e-30..1e30 (ratios up to 1e30)");
     }
     if (f8 && cfg == 4) cfg = 1;  // no wave kernel for FP8 operands
     P->kt = P->padded ? 32 : (P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16);
@@ -2055,7 +2068,7 @@ class HipExec : public Executor {
         (std::getenv("DMRG_TUNE") && std::atoi(std::getenv("DMRG_TUNE")) == 0) || std::getenv("DMRG_TILE") ||
         std::getenv("DMRG_WAVE") || std::getenv("DMRG_NO_PADDED_KERNEL"))
       return prepare(jobs, terms, da, db, dc);
-    const std::string key = tune_key(jobs, terms, dc);
+    const std::string key = tune_key(jobs, terms, da, db, dc);
     std::lock_guard<std::mutex> lock(tune_mu());
     load_tune_file();
     auto it = tune_map().find(key);
@@ -2298,8 +2311,12 @@ class HipExec : public Executor {
       hipLaunchKernelGGL(absmax_partial, dim3(nb, ny), dim3(256), 0, stream_, src + y0 * seg, (long long)seg,
                          (long long)seg, part + y0 * nb);
     }
+    // Operator segments of at most 1e-13 (round-off of the FP64 block
+    // build; operators are in Hartree units) are flushed to zero: far below
+    // the E4M3 resolution of any product they enter, and a scale that small
+    // would push the folded product weights out of the kernel's range.
     hipLaunchKernelGGL(pow2_scale, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, stream_, part, nb, (int)nseg,
-                       d_scale);
+                       d_scale, 1e-13);
     HIP_OK(hipGetLastError());
     sync();
     release(part);
@@ -2319,7 +2336,7 @@ class HipExec : public Executor {
     if (!fp8_part_) fp8_part_ = (double*)alloc(1024 * sizeof(double));
     hipLaunchKernelGGL(absmax_partial, dim3(nb, 1), dim3(256), 0, stream_, src_all, (long long)n_all, (long long)n_all,
                        fp8_part_);
-    hipLaunchKernelGGL(pow2_scale, dim3(1), dim3(1), 0, stream_, fp8_part_, nb, 1, d_scale);
+    hipLaunchKernelGGL(pow2_scale, dim3(1), dim3(1), 0, stream_, fp8_part_, nb, 1, d_scale, 0.0);
     const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(pack_fp8_kernel, dim3(grid), dim3(256), 0, stream_, (unsigned char*)dst, src, idx, (long long)n,
                        d_scale);
@@ -2479,7 +2496,8 @@ class HipExec : public Executor {
     static int n = 0;
     return n;
   }
-  static std::string tune_key(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int dc) {
+  static std::string tune_key(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db,
+                              int dc) {
     double work = 0.0, sm = 0.0, sn = 0.0, sk = 0.0, nk = 0.0;
     for (const RawJob& J : jobs) {
       sm += J.m;
@@ -2496,7 +2514,8 @@ class HipExec : public Executor {
     const double nj = (double)jobs.size();
     auto b2 = [](double x) { return (int)std::lround(std::log2(std::max(x, 1.0))); };
     char buf[128];
-    std::snprintf(buf, sizeof buf, "dc%d_w%d_j%d_m%d_n%d_k%d", dc, b2(work), b2(nj), b2(sm / nj), b2(sn / nj),
+    std::snprintf(buf, sizeof buf, "a%d_b%d_c%d_w%d_j%d_m%d_n%d_k%d", da, db, dc, b2(work), b2(nj), b2(sm / nj),
+                  b2(sn / nj),
                   b2(nk > 0 ? sk / nk : 1.0));
     return buf;
   }
