@@ -186,7 +186,15 @@ int dmrg_heff_diag(dmrg_ctx *c, int k, double *diag);
  * On return psi_inout holds the normalised eigenvector, energy the
  * eigenvalue plus e_core, resid_norm ||H x - E x||_2; n_matvec_lowprec counts
  * every hpsi_prec matvec (inner solves included), n_matvec_fp64 the FP64 ones.
- * Returns NOCONV (outputs still written) if tol is not reached. */
+ * Returns NOCONV (outputs still written) if tol is not reached.
+ *
+ * Step log: if the environment variable DMRG_LOG names a file, every
+ * dmrg_davidson_step and dmrg_truncate(_dbss) that returns OK (or NOCONV for
+ * Davidson) appends one JSON object per line to it -- for Davidson the block,
+ * length, precision, energy, residual, matvec counts, H*psi flops, wall
+ * seconds and the host seconds spent planning and preparing task lists; for
+ * a truncation the block, direction, multiplets D and U(1) states D~ of the
+ * new bond, discarded weight, wall seconds and the next block. */
 int dmrg_davidson_step(dmrg_ctx *c, int k, double *psi_inout, double *energy, double *resid_norm,
                        int *n_matvec_lowprec, int *n_matvec_fp64);
 

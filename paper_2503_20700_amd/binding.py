@@ -197,6 +197,16 @@ def gemm_selftest(A, B, C=None, trans_a=False, trans_b=False, ident_a=False, ide
     return C
 
 
+def load_checkpoint(path):
+    """Contents of a save_checkpoint file as a dict (plain arrays; nothing
+    in the file is executed)."""
+    with np.load(path, allow_pickle=False) as z:
+        out = {key: z[key] for key in z.files}
+    for key in ("k", "n_orb", "n_elec", "two_s"):
+        out[key] = int(out[key])
+    return out
+
+
 def _dp(a):
     return a.ctypes.data_as(ct.POINTER(ct.c_double))
 
@@ -345,6 +355,36 @@ class DMRG:
         out = np.zeros(max(n.value, 1))
         self._check(self.lib.dmrg_get_site(self._h, j, _dp(out), ct.byref(n)))
         return out[:n.value]
+
+    def save_checkpoint(self, path, psi):
+        """Write the MPS around the current two-site block (k, k+1) to one
+        .npz file: the sectors of bonds 0..n (bond k+1, inside the block,
+        empty), the site tensors outside the block (dmrg_get_site, in the
+        order dmrg_set_mps reads them), the two-site psi and the system's
+        orbital / electron / spin numbers.  resume() reloads it."""
+        n, k = self.opts.n_orb, self.k
+        rows, counts = [], []
+        for b in range(n + 1):
+            secs = [] if b == k + 1 else self.get_bond(b)
+            counts.append(len(secs))
+            rows.extend(secs)
+        sites = [self.get_site(j) for j in range(n) if j not in (k, k + 1)]
+        np.savez(path, k=np.int64(k), n_orb=np.int64(n), n_elec=np.int64(self.opts.n_elec),
+                 two_s=np.int64(self.opts.two_s), bond_sectors=np.asarray(rows, dtype=np.int32).reshape(-1, 3),
+                 counts=np.asarray(counts, dtype=np.int32),
+                 sites=np.concatenate(sites) if sites else np.zeros(0),
+                 psi=np.ascontiguousarray(psi, dtype=np.float64))
+
+    def resume(self, path):
+        """Load a checkpoint written by save_checkpoint into this context
+        (same orbitals, electrons and spin; its integrals are this
+        context's): builds the operator blocks around the saved block and
+        returns the saved psi."""
+        ck = load_checkpoint(path)
+        if (ck["n_orb"], ck["n_elec"], ck["two_s"]) != (self.opts.n_orb, self.opts.n_elec, self.opts.two_s):
+            raise ValueError("checkpoint is for a different system (orbitals, electrons or spin)")
+        self.set_mps(ck["k"], ck["bond_sectors"], ck["counts"], ck["sites"])
+        return ck["psi"]
 
     def cut_spectrum(self, capacity=1 << 20):
         vals = np.zeros(capacity)

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <mutex>
 #include <random>
 #include <tuple>
 #include <string>
@@ -357,10 +358,58 @@ Workspace workspace(dmrg_ctx* c, int64_t n, int mmax) {
 }
 }  // namespace
 
+void step_log(const std::string& json) {
+  const char* path = std::getenv("DMRG_LOG");
+  if (!path || !*path) return;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s\n", json.c_str());
+    std::fclose(f);
+  }
+}
+
+namespace {
+const char* prec_name(int p) {
+  return p == DMRG_FP64 ? "fp64" : p == DMRG_FP32 ? "fp32" : p == DMRG_BF16 ? "bf16" : "fp8";
+}
+// Multiplets D and U(1) states (sum of dim * (2S+1)) of bond b.
+std::pair<long long, long long> bond_dims(const Context& C, int b) {
+  long long d = 0, du = 0;
+  if (b >= 0 && b < (int)C.bonds.size())
+    for (const auto& s : C.bonds[b].secs) {
+      d += s.dim;
+      du += (long long)s.dim * (s.s2 + 1);
+    }
+  return {d, du};
+}
+}  // namespace
+
 extern "C" int dmrg_davidson_step(dmrg_ctx* c, int k, double* psi, double* energy, double* resid, int* nlo, int* nhi) {
   if (!c || !psi || !energy || !resid) return dmrg_fail(DMRG_ERR_ARG, "dmrg_davidson_step: null argument");
   if (!c->C->Lblk || k != c->C->k) return dmrg_fail(DMRG_ERR_ARG, "dmrg_davidson_step: no MPS loaded at this k");
-  return davidson_core(c, psi, energy, resid, nlo, nhi);
+  const long long serial = c->plan_serial;
+  const auto t0 = std::chrono::steady_clock::now();
+  int lo = 0, hi = 0;
+  const int rc = davidson_core(c, psi, energy, resid, &lo, &hi);
+  if (nlo) *nlo = lo;
+  if (nhi) *nhi = hi;
+  if (std::getenv("DMRG_LOG") && (rc == DMRG_OK || rc == DMRG_ERR_NOCONV) && c->plan) {
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    char buf[768];
+    std::snprintf(buf, sizeof buf,
+                  "{\"event\": \"davidson\", \"block\": [%d, %d], \"n_coeff\": %lld, \"precision\": \"%s\", "
+                  "\"energy\": %.12f, \"residual\": %.3e, \"converged\": %s, \"matvecs_lowprec\": %d, "
+                  "\"matvecs_fp64\": %d, \"hpsi_flops\": %.6e, \"seconds\": %.3f, \"plan_seconds\": %.3f, "
+                  "\"prepare_seconds\": %.3f}",
+                  k, k + 1, (long long)c->plan->lay.size, prec_name(c->opts.hpsi_prec), *energy, *resid,
+                  rc == DMRG_OK ? "true" : "false", lo, hi, c->plan->flops, sec,
+                  c->plan_serial != serial ? c->plan_seconds : 0.0,
+                  c->prepare_seconds[0] + c->prepare_seconds[1] + c->prepare_seconds[2] + c->prepare_seconds[3]);
+    for (double& x : c->prepare_seconds) x = 0.0;  // each preparation is reported once
+    step_log(buf);
+  }
+  return rc;
 }
 
 int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* nlo, int* nhi) {
@@ -540,8 +589,28 @@ extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int
   return dmrg_truncate_dbss(c, k, psi, dir, 0, d_max, eps_tr, trunc_err, d_kept);
 }
 
+static int truncate_core(dmrg_ctx* c, int k, const double* psi, int dir, int d_min, int d_max, double eps_tr,
+                         double* trunc_err, int* d_kept);
+
 extern "C" int dmrg_truncate_dbss(dmrg_ctx* c, int k, const double* psi, int dir, int d_min, int d_max,
                                   double eps_tr, double* trunc_err, int* d_kept) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = truncate_core(c, k, psi, dir, d_min, d_max, eps_tr, trunc_err, d_kept);
+  if (rc == DMRG_OK && std::getenv("DMRG_LOG")) {
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const auto dd = bond_dims(*c->C, k + 1);
+    char buf[512];
+    std::snprintf(buf, sizeof buf,
+                  "{\"event\": \"truncate\", \"block\": [%d, %d], \"direction\": %d, \"bond\": %d, "
+                  "\"d_kept\": %d, \"d_u1\": %lld, \"trunc_err\": %.6e, \"seconds\": %.3f, \"next_block\": %d}",
+                  k, k + 1, dir, k + 1, *d_kept, dd.second, *trunc_err, sec, c->C->k);
+    step_log(buf);
+  }
+  return rc;
+}
+
+static int truncate_core(dmrg_ctx* c, int k, const double* psi, int dir, int d_min, int d_max, double eps_tr,
+                         double* trunc_err, int* d_kept) {
   if (!c || !psi || !trunc_err || !d_kept) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: null argument");
   if (dir != 1 && dir != -1) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: direction must be +1 or -1");
   if (d_max < 1 || !(eps_tr >= 0.0)) return dmrg_fail(DMRG_ERR_ARG, "dmrg_truncate: bad d_max / eps_tr");

@@ -1,6 +1,7 @@
 // Per-context state behind the C ABI: executor, planner context, the H*psi
 // plan of the current two-site block and its device buffers.
 #pragma once
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
@@ -19,6 +20,9 @@ struct dmrg_ctx;
 // The Davidson solve of dmrg_davidson_step at the context's current block
 // (argument checks done by the caller); returns a dmrg error code.
 int davidson_core(dmrg_ctx* c, double* psi, double* energy, double* resid, int* nlo, int* nhi);
+// Appends one JSON object (without newline) as a line to the file that the
+// environment variable DMRG_LOG names; nothing if it is unset.
+void step_log(const std::string& json);
 
 // psi_in, psi_out, X, ones, diag and padded-psi_in placeholders used by the
 // H*psi task lists
@@ -36,6 +40,9 @@ struct dmrg_ctx {
   void* d_uidx = nullptr;  // caller index -> index in b_outp (int32)
   double* d_pscale = nullptr;  // (s, 1/s) of the FP8 copy of psi_in
   long long plan_serial = 0;  // bumped whenever a new H*psi plan is made
+  // host seconds of the last H*psi plan, and of the task-list preparations
+  // (incl. tile tuning) per precision since the step log last reported them
+  double plan_seconds = 0.0, prepare_seconds[4] = {0.0, 0.0, 0.0, 0.0};
   // start vector carried by the last truncation to the block it moved to
   std::vector<double> guess;
   int guess_k = -1;
@@ -119,7 +126,9 @@ struct dmrg_ctx {
 
   void ensure_plan() {
     if (plan) return;
+    const auto t0 = std::chrono::steady_clock::now();
     plan = C->plan_hpsi(budget());
+    plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     ++plan_serial;
     const int64_t n = plan->lay.size;
     b_in = C->new_buf(std::max<int64_t>(n, 1));
@@ -242,6 +251,7 @@ struct dmrg_ctx {
   void prepare(int prec) {
     Prepared& P = prep[prec];
     if (P.ready) return;
+    const auto t0 = std::chrono::steady_clock::now();
     const int od = op_dt(prec), xd = x_dt(prec), outd = out_dt(prec);
     ready_dtypes(prec);
     bind();
@@ -254,6 +264,7 @@ struct dmrg_ctx {
       P.R.push_back(ex->prepare_tuned(j, t, xd, od, outd));
     }
     P.ready = true;
+    prepare_seconds[prec] += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 
   // Before the stage launches (on executor e): the padded operand copy of
