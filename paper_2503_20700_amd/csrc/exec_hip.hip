@@ -542,8 +542,96 @@ __global__ __launch_bounds__(256) void gemm_kernel(const RawJob* __restrict__ jo
 // the register budget is capped to keep more waves resident: 7 per SIMD for
 // 64 x 64 tiles and 4 for the larger ones, the most that compile without
 // spilling to scratch.
+// Identity products of a work item of the padded BF16 kernels: acc +=
+// alpha * (the other operand) over the tile, in the unscaled frame (before
+// any dense product).  Wave quadrant (wm, wn), MFMA lane coordinates lr, lg.
+template <int BM, int BN, bool AF8, bool BF8>
+__device__ __forceinline__ void tile_identity_products(f4 (&acc)[BM / 32][BN / 32], const WorkItem& W, const RawJob& J,
+                                                       const RawTerm* __restrict__ terms, int m0, int n0, int wm,
+                                                       int wn, int lr, int lg) {
+  constexpr int FA = BM / 32, FB = BN / 32;
+  for (int t = W.tbeg; t < W.tend; ++t) {
+    const int fl = terms[t].flags;
+    if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+    const RawTerm T = terms[t];
+    const bool ia = fl & TF_IDENT_A;
+    const void* P = ia ? T.B : T.A;
+    const bool f8 = ia ? BF8 : AF8;
+    const long long ld = ia ? T.ldb : T.lda;
+    const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int b = 0; b < FB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = m0 + wm + a * 16 + 4 * lg + v;
+          const int col = n0 + wn + b * 16 + lr;
+          if (row < J.m && col < J.n) {
+            const long long e = tr ? (long long)col * ld + row : (long long)row * ld + col;
+            acc[a][b][v] += (float)T.alpha * (f8 ? fp8_to_f(((const unsigned char*)P)[e]) : bf2f(((const u16*)P)[e]));
+          }
+        }
+  }
+}
+
+// Write-back of a BM x BN tile of the padded BF16 kernels: into C (BF16
+// output tiles with aligned rows staged through smem and stored as 16-byte
+// vectors), or into the item's partial slot.  smem must hold BM x BN u16 and
+// may still be read by other waves on entry.
+template <int DC, int BM, int BN>
+__device__ __forceinline__ void tile_store(const f4 (&acc)[BM / 32][BN / 32], const WorkItem& W, const RawJob& J,
+                                           u16* smem, void* __restrict__ part, int m0, int n0, int wm, int wn,
+                                           int lr, int lg, int tid) {
+  constexpr int FA = BM / 32, FB = BN / 32;
+  if constexpr (DC == DT_BF16) {
+    if (W.slot < 0 && !J.accumulate && (((uintptr_t)J.C) & 15) == 0 && (J.ldc & 7) == 0 && (J.n & 7) == 0) {
+      __syncthreads();  // every wave is done reading the last slab
+#pragma unroll
+      for (int a = 0; a < FA; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) smem[(wm + a * 16 + 4 * lg + v) * BN + wn + b * 16 + lr] = f2bf(acc[a][b][v]);
+      __syncthreads();
+      constexpr int VPR = BN / 8;  // vectors per tile row
+#pragma unroll
+      for (int i = tid; i < BM * VPR; i += 256) {
+        const int r = i / VPR, c8 = (i % VPR) * 8;
+        if (m0 + r < J.m && n0 + c8 < J.n)
+          *(uint4*)((u16*)J.C + (long long)(m0 + r) * J.ldc + n0 + c8) = *(const uint4*)(smem + r * BN + c8);
+      }
+      return;
+    }
+  }
+  if (W.slot >= 0) {
+    float* P = (float*)part + (long long)W.slot * (BM * BN);
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int b = 0; b < FB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[(wm + a * 16 + 4 * lg + v) * BN + wn + b * 16 + lr] = acc[a][b][v];
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < FA; ++a)
+#pragma unroll
+    for (int b = 0; b < FB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + a * 16 + 4 * lg + v;
+        const int col = n0 + wn + b * 16 + lr;
+        if (row < J.m && col < J.n) {
+          const long long o = (long long)row * J.ldc + col;
+          if (J.accumulate) stv<DC>(J.C, o, ldv<DC>(J.C, o) + (double)acc[a][b][v]);
+          else stv<DC>(J.C, o, acc[a][b][v]);
+        }
+      }
+}
+
 template <int DC, int BM, int BN, bool AF8 = false, bool BF8 = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4096 ? 4 : 7))) void gemm_bf16_padded(const RawJob* __restrict__ jobs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 8192 ? 2 : (BM * BN > 4096 ? 4 : 7)))) void gemm_bf16_padded(const RawJob* __restrict__ jobs,
                                                         const RawTerm* __restrict__ terms,
                                                         const WorkItem* __restrict__ items, void* __restrict__ part) {
   constexpr int KT = 32, LS = KT + 8;     // LDS row stride in bf16 elements (80 bytes)
@@ -568,30 +656,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4
 #pragma unroll
     for (int b = 0; b < FB; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
   // identity products, in the unscaled frame
-  if (W.has_ident)
-    for (int t = W.tbeg; t < W.tend; ++t) {
-      const int fl = terms[t].flags;
-      if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
-      const RawTerm T = terms[t];
-      const bool ia = fl & TF_IDENT_A;
-      const void* P = ia ? T.B : T.A;
-      const bool f8 = ia ? BF8 : AF8;
-      const long long ld = ia ? T.ldb : T.lda;
-      const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
-#pragma unroll
-      for (int a = 0; a < FA; ++a)
-#pragma unroll
-        for (int b = 0; b < FB; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = m0 + wm + a * 16 + 4 * lg + v;
-            const int col = n0 + wn + b * 16 + lr;
-            if (row < J.m && col < J.n) {
-              const long long e = tr ? (long long)col * ld + row : (long long)row * ld + col;
-              acc[a][b][v] += (float)T.alpha * (f8 ? fp8_to_f(((const unsigned char*)P)[e]) : bf2f(((const u16*)P)[e]));
-            }
-          }
-    }
+  if (W.has_ident) tile_identity_products<BM, BN, AF8, BF8>(acc, W, J, terms, m0, n0, wm, wn, lr, lg);
   auto lds_at = [](int j, int k) { return j * LS + 8 * ((k >> 3) ^ ((j >> 4) & 3)) + (k & 7); };
   // thread roles for vector v of an operand with R rows (R = BM or BN):
   //   "K":  row (tid + 256 v) >> 2, k offset ((tid + 256 v) & 3) * 8
@@ -785,53 +850,231 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 4
 #pragma unroll
       for (int b = 0; b < FB; ++b) acc[a][b] *= scale;
   }
-  // write back (C, or the item's partial slot of BM x BN values)
-  if constexpr (DC == DT_BF16) {
-    // BF16 output with 16-byte aligned rows of a multiple of 8 columns
-    // (the X intermediates): stage the tile in LDS, store 16-byte vectors
-    if (W.slot < 0 && !J.accumulate && (((uintptr_t)J.C) & 15) == 0 && (J.ldc & 7) == 0 && (J.n & 7) == 0) {
-      __syncthreads();  // every wave is done reading the last slab
-#pragma unroll
-      for (int a = 0; a < FA; ++a)
-#pragma unroll
-        for (int b = 0; b < FB; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) smem[(wm + a * 16 + 4 * lg + v) * BN + wn + b * 16 + lr] = f2bf(acc[a][b][v]);
-      __syncthreads();
-      constexpr int VPR = BN / 8;  // vectors per tile row
-#pragma unroll
-      for (int i = tid; i < BM * VPR; i += 256) {
-        const int r = i / VPR, c8 = (i % VPR) * 8;
-        if (m0 + r < J.m && n0 + c8 < J.n)
-          *(uint4*)((u16*)J.C + (long long)(m0 + r) * J.ldc + n0 + c8) = *(const uint4*)(smem + r * BN + c8);
-      }
-      return;
-    }
-  }
-  if (W.slot >= 0) {
-    float* P = (float*)part + (long long)W.slot * (BM * BN);
-#pragma unroll
-    for (int a = 0; a < FA; ++a)
-#pragma unroll
-      for (int b = 0; b < FB; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) P[(wm + a * 16 + 4 * lg + v) * BN + wn + b * 16 + lr] = acc[a][b][v];
-    return;
-  }
+  tile_store<DC, BM, BN>(acc, W, J, smem, part, m0, n0, wm, wn, lr, lg, tid);
+}
+
+// 16 bytes per lane from global memory straight into LDS: lane l of the
+// wave writes LDS bytes [lds + 16 l, lds + 16 l + 16) (lds: wave-uniform
+// byte address).  Written as inline assembly so that the compiler, which
+// cannot tell the pipeline stages apart, does not add its own wait for every
+// outstanding LDS write before each LDS read; the kernel orders them itself
+// with pipe_wait_barrier.  No register is written, so nothing is left in
+// flight behind the compiler's back.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"  // m0 is set here on purpose
+__device__ __forceinline__ void lds_dma16(const void* g, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" ::"s"(lds), "v"(g) : "m0");
+}
+#pragma clang diagnostic pop
+// Wait until at most N of this wave's vector-memory operations are in
+// flight and its LDS reads are done, then a work-group barrier (and a
+// compiler memory barrier).
+template <int N>
+__device__ __forceinline__ void pipe_wait_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+// Padded BF16 grouped GEMM with an S-stage LDS pipeline: the same work items,
+// products, scaled accumulator frame, identity products and write-back as
+// gemm_bf16_padded, but every operand slab (32 k wide) is copied from global
+// memory into its own LDS stage by LDS DMA (no staging registers), S - 1
+// slabs ahead of the MFMAs, so each work-group keeps several slabs in
+// flight.  LDS layouts per stage and operand (R = BM or BN rows):
+//   * stored along k (A not transposed, B transposed): R rows of 32 k in
+//     four 16-byte chunks, chunk q of row r at slot q ^ ((r >> 2) & 3);
+//   * stored along m or n: 32 k rows of R elements in R / 8 chunks, chunk q
+//     of k row k at slot q ^ ((k >> 3) & (R / 8 - 1)) (conflict-free
+//     reads of the four k groups of an MFMA operand).
+// Each wave copies R / 64 consecutive 1 KB pieces of each operand slab.
+// Lanes outside the operand (rows past m or n, k chunks past K) copy the
+// operand's first 16 bytes instead, so every wave issues the same number of
+// copies per slab and the waits count them exactly; those LDS cells only
+// reach rows and columns that are not written back (past m or n), or are
+// zeroed in registers (k past K) before the MFMA.
+template <int DC, int BM, int BN, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 8192 ? 2 : (BM * BN > 4096 ? 3 : 5)))) void gemm_bf16_pipe(
+    const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms, const WorkItem* __restrict__ items,
+    void* __restrict__ part) {
+  constexpr int KT = 32;
+  constexpr int FA = BM / 32, FB = BN / 32;  // 16x16 MFMA blocks per wave along m / n
+  constexpr int NA = BM / 64, NB = BN / 64;  // 1 KB copies per wave per slab
+  constexpr int NI = NA + NB;
+  constexpr int SA = BM * KT, STG = (BM + BN) * KT;  // u16 elements: A part of a stage, a stage
+  static_assert(S >= 2 && S <= 4, "pipeline depth");
+  __shared__ __attribute__((aligned(16))) u16 smem[S * STG];
+  static_assert(BM * BN <= S * STG, "output tile must fit the stages");
+  const int tid = threadIdx.x;
+  const WorkItem W = items[blockIdx.x];
+  const RawJob J = jobs[W.job];
+  const int m0 = W.ti * BM, n0 = W.tj * BN;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int lr = lane & 15, lg = lane >> 4;
+
+  f4 acc[FA][FB];
 #pragma unroll
   for (int a = 0; a < FA; ++a)
 #pragma unroll
-    for (int b = 0; b < FB; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = m0 + wm + a * 16 + 4 * lg + v;
-        const int col = n0 + wn + b * 16 + lr;
-        if (row < J.m && col < J.n) {
-          const long long o = (long long)row * J.ldc + col;
-          if (J.accumulate) stv<DC>(J.C, o, ldv<DC>(J.C, o) + (double)acc[a][b][v]);
-          else stv<DC>(J.C, o, acc[a][b][v]);
-        }
+    for (int b = 0; b < FB; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  if (W.has_ident) tile_identity_products<BM, BN, false, false>(acc, W, J, terms, m0, n0, wm, wn, lr, lg);
+
+  // Product records are read through the constant address space, which
+  // makes the compiler use scalar loads for them (counted apart from the
+  // vector-memory operations the pipeline waits on): a vector load of a
+  // record inside the K loop would come with a wait for every slab in
+  // flight.
+  typedef const __attribute__((address_space(4))) RawTerm CTerm;
+  CTerm* cterms = (CTerm*)(uintptr_t)terms;
+  auto next_dense = [&](int t) {
+    while (t < W.tend && ((cterms[t].flags & (TF_IDENT_A | TF_IDENT_B)) || cterms[t].k <= 0)) ++t;
+    return t;
+  };
+  const unsigned lds0 = (unsigned)(uintptr_t)smem;
+  // ---- loader: product tl, slab kl
+  int tl = next_dense(W.dense0), kl = 0;
+  const u16* LA = nullptr;
+  const u16* LB = nullptr;
+  long long lda = 0, ldb = 0;
+  int lK = 0;
+  bool laK = true, lbK = true;
+  auto load_term = [&]() {
+    CTerm& T = cterms[tl];
+    LA = (const u16*)T.A;
+    LB = (const u16*)T.B;
+    lda = T.lda;
+    ldb = T.ldb;
+    lK = T.k;
+    const int fl = T.flags;
+    laK = !(fl & TF_TRANS_A);  // A stored m x k
+    lbK = (fl & TF_TRANS_B);   // B stored n x k
+  };
+  if (tl < W.tend) load_term();
+  // one operand's copies of slab kl into LDS byte address dst
+  auto copy_operand = [&](const u16* P, long long ld, bool alongK, int R, int r0, int ext, int nv, unsigned dst) {
+    for (int v = 0; v < nv; ++v) {
+      const int c = wave * nv + v;  // 1 KB piece of the slab
+      const int pz = c * 64 + lane;  // 16-byte slot
+      const u16* g = P;
+      if (alongK) {
+        const int row = pz >> 2, q = (pz & 3) ^ ((row >> 2) & 3);
+        if (r0 + row < ext && kl + 8 * q < lK) g = P + (long long)(r0 + row) * ld + kl + 8 * q;
+      } else {
+        const int cpr = R / 8, kr = pz / cpr, q = (pz % cpr) ^ ((kr >> 3) & (cpr - 1));
+        if (kl + kr < lK && r0 + 8 * q < ext) g = P + (long long)(kl + kr) * ld + r0 + 8 * q;
       }
+      lds_dma16(g, __builtin_amdgcn_readfirstlane(dst + c * 1024));
+    }
+  };
+  auto issue = [&](int st) {
+    const unsigned base = lds0 + (unsigned)(st * STG) * 2u;
+    copy_operand(LA, lda, laK, BM, m0, J.m, NA, base);
+    copy_operand(LB, ldb, lbK, BN, n0, J.n, NB, base + SA * 2u);
+    kl += KT;
+    if (kl >= lK) {
+      tl = next_dense(tl + 1);
+      kl = 0;
+      if (tl < W.tend) load_term();
+    }
+  };
+  int issued = 0;
+#pragma unroll
+  for (int s0 = 0; s0 < S - 1; ++s0)
+    if (tl < W.tend) {
+      issue(s0);
+      ++issued;
+    }
+  // ---- consumer: product tc, slab kc
+  int tc = next_dense(W.dense0), kc = 0, cK = 0;
+  bool caK = true, cbK = true;
+  float alpha = 1.f, scale = 1.f;
+  auto use_term = [&]() {
+    CTerm& T = cterms[tc];
+    cK = T.k;
+    const int fl = T.flags;
+    caK = !(fl & TF_TRANS_A);
+    cbK = (fl & TF_TRANS_B);
+    alpha = (float)T.alpha;
+  };
+  if (tc < W.tend) use_term();
+  // LDS element offsets of this lane's MFMA operands (k group lg)
+  auto offK = [&](int r) { return r * KT + 8 * (lg ^ ((r >> 2) & 3)); };
+  auto offMN = [&](int R, int k, int r) { return k * R + 8 * ((r >> 3) ^ ((k >> 3) & (R / 8 - 1))) + (r & 7); };
+  int i = 0;
+  while (tc < W.tend) {
+    const int st = i % S;
+    const int ahead = issued - i - 1;  // slabs issued after slab i, 0 .. S - 2
+    if (S >= 4 && ahead >= 2) pipe_wait_barrier<2 * NI>();
+    else if (S >= 3 && ahead >= 1) pipe_wait_barrier<NI>();
+    else pipe_wait_barrier<0>();
+    if (tl < W.tend) {
+      issue(issued % S);  // the stage slab i - 1 used; every wave is past it
+      ++issued;
+    }
+    if (kc == 0 && alpha != scale) {  // product tc starts: move acc into its frame
+      const float r = scale / alpha;
+#pragma unroll
+      for (int a = 0; a < FA; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b) acc[a][b] *= r;
+      scale = alpha;
+    }
+    const u16* sA = smem + st * STG;
+    const u16* sB = sA + SA;
+    bf8 av[FA], bv[FB];
+#pragma unroll
+    for (int a = 0; a < FA; ++a) {
+      const int r = wm + a * 16 + lr;
+      if (caK) {
+        av[a] = *(const bf8*)(sA + offK(r));
+      } else {
+        u16 e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[j] = sA[offMN(BM, 8 * lg + j, r)];
+        av[a] = __builtin_bit_cast(bf8, e);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < FB; ++b) {
+      const int r = wn + b * 16 + lr;
+      if (cbK) {
+        bv[b] = *(const bf8*)(sB + offK(r));
+      } else {
+        u16 e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[j] = sB[offMN(BN, 8 * lg + j, r)];
+        bv[b] = __builtin_bit_cast(bf8, e);
+      }
+    }
+    const int nvk = cK - kc - 8 * lg;  // valid k of this lane's eight
+    if (nvk < 8) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j >= nvk) {
+#pragma unroll
+          for (int a = 0; a < FA; ++a) av[a][j] = (__bf16)0.f;
+#pragma unroll
+          for (int b = 0; b < FB; ++b) bv[b][j] = (__bf16)0.f;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int b = 0; b < FB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    ++i;
+    kc += KT;
+    if (kc >= cK) {
+      tc = next_dense(tc + 1);
+      kc = 0;
+      if (tc < W.tend) use_term();
+    }
+  }
+  if (scale != 1.f) {
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int b = 0; b < FB; ++b) acc[a][b] *= scale;
+  }
+  tile_store<DC, BM, BN>(acc, W, J, smem, part, m0, n0, wm, wn, lr, lg, tid);
 }
 
 // BF16 kernel for padded launches dominated by small blocks (many output
@@ -1621,6 +1864,7 @@ struct Prepared {
   int mode = DT_F64, da = DT_F64, db = DT_F64, dc = DT_F64, kt = 16;
   bool padded = false;  // BF16 launch served by gemm_bf16_padded
   bool wave = false;    // ... or by gemm_bf16_wave (32 x 32 tile per wave)
+  bool pipe = false;    // ... or by gemm_bf16_pipe (LDS DMA pipeline)
   int bm = TM, bn = TN;  // output tile of the launch
   void* part = nullptr;  // partial tiles of a fixed-scratch launch (else the executor's)
   // fixed-scratch launches: task lists kept on the host until placed
@@ -1648,6 +1892,7 @@ KernelFn pick_padded(int dc, int bm, int bn, bool af8 = false, bool bf8 = false)
   if (dc == D && bm == M && bn == N && af8 == FA && bf8 == FB) return gemm_bf16_padded<D, M, N, FA, FB>;
   P_(DT_BF16, 64, 64, false, false) P_(DT_BF16, 64, 128, false, false) P_(DT_BF16, 128, 64, false, false)
   P_(DT_F32, 64, 64, false, false) P_(DT_F32, 64, 128, false, false) P_(DT_F32, 128, 64, false, false)
+  P_(DT_BF16, 128, 128, false, false) P_(DT_F32, 128, 128, false, false)
   // FP8 operands: stage L (operator blocks and psi in FP8, X out in BF16),
   // stage R (X in BF16, operator blocks in FP8, psi' out in FP32)
   P_(DT_BF16, 64, 64, true, true) P_(DT_BF16, 64, 128, true, true) P_(DT_BF16, 128, 64, true, true)
@@ -1658,13 +1903,29 @@ KernelFn pick_padded(int dc, int bm, int bn, bool af8 = false, bool bf8 = false)
   throw std::runtime_error("executor: unsupported tile shape or FP8 operand combination");
 }
 
+// The LDS-pipelined kernel for a tile (BF16 operands only); the stage count
+// keeps the LDS of a work-group at 32-48 KB.
+KernelFn pick_pipe(int dc, int bm, int bn) {
+#define P_(D, M, N, S) \
+  if (dc == D && bm == M && bn == N) return gemm_bf16_pipe<D, M, N, S>;
+  P_(DT_BF16, 64, 64, 4) P_(DT_BF16, 64, 128, 3) P_(DT_BF16, 128, 64, 3) P_(DT_BF16, 128, 128, 3)
+  P_(DT_F32, 64, 64, 4) P_(DT_F32, 64, 128, 3) P_(DT_F32, 128, 64, 3) P_(DT_F32, 128, 128, 3)
+#undef P_
+  throw std::runtime_error("executor: unsupported tile shape for the pipelined kernel");
+}
+
 // Output tile of a padded BF16 launch.  Candidates 64x64, 64x128 and 128x64:
 // among those whose padded MFMA work (tiles x tile area x K rounded to 32)
 // is within 10 % of the smallest, the one with the fewest tiles (less fixed
-// cost per item, more reuse of each staged slab).  DMRG_TILE=MxN overrides.
+// cost per item, more reuse of each staged slab).  DMRG_TILE=MxN overrides
+// (also 128x128, which only the tuner picks otherwise).
 void choose_tile(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int& bm, int& bn) {
   const int cand[3][2] = {{64, 64}, {64, 128}, {128, 64}};
   if (const char* e = std::getenv("DMRG_TILE")) {
+    if (std::string(e) == "128x128") {
+      bm = bn = 128;
+      return;
+    }
     for (auto& c : cand)
       if (std::string(e) == std::to_string(c[0]) + "x" + std::to_string(c[1])) {
         bm = c[0];
@@ -1979,7 +2240,9 @@ class HipExec : public Executor {
   }
   // Kernel choice and work items of a launch (host only).
   // cfg (padded BF16 launches only): 0 the static rule (choose_wave /
-  // choose_tile), 1..3 the tiles 64x64, 64x128, 128x64, 4 the wave kernel.
+  // choose_tile), 1..3 the tiles 64x64, 64x128, 128x64, 4 the wave kernel,
+  // 5 the tile 128x128, 6..9 the LDS-pipelined kernel with tiles 64x64,
+  // 64x128, 128x64, 128x128 (5..9: BF16 operands only).
   Prepared* configure(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc,
                       std::vector<WorkItem>& items, std::vector<RedItem>& reds, int cfg = 0) {
     auto* P = new Prepared();
@@ -2017,11 +2280,21 @@ class HipExec : public Executor {
       throw std::runtime_error(
           "executor: FP8 operands need padded, aligned operands and weights within 1e-30..1e30 (ratios up to 1e30)");
     }
-    if (f8 && cfg == 4) cfg = 1;  // no wave kernel for FP8 operands
+    if (f8 && cfg >= 4) cfg = 1;  // FP8 operands: the three smaller register-staged tiles only
+    if (P->padded && cfg == 0 && !f8) {  // forced from the environment (tests, experiments)
+      const char* e = std::getenv("DMRG_TILE");
+      if (e && std::string(e).rfind("pipe", 0) == 0) {
+        const std::string t(e + 4);
+        cfg = t == "64x64" ? 6 : t == "64x128" ? 7 : t == "128x64" ? 8 : t == "128x128" ? 9 : 0;
+        if (!cfg) throw std::runtime_error("executor: DMRG_TILE=pipeMxN takes 64x64, 64x128, 128x64 or 128x128");
+      }
+    }
     P->kt = P->padded ? 32 : (P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16);
     if (P->padded && cfg > 0) {
-      static const int tiles[4][2] = {{64, 64}, {64, 128}, {128, 64}, {32, 32}};
+      static const int tiles[9][2] = {{64, 64}, {64, 128}, {128, 64}, {32, 32}, {128, 128},
+                                      {64, 64}, {64, 128}, {128, 64}, {128, 128}};
       P->wave = cfg == 4;
+      P->pipe = cfg >= 6;
       P->bm = tiles[cfg - 1][0];
       P->bn = tiles[cfg - 1][1];
     } else if (P->padded) {
@@ -2052,7 +2325,8 @@ class HipExec : public Executor {
     return prepare_cfg(jobs, terms, da, db, dc, 0);
   }
   // Measured choice of the kernel configuration of a padded BF16 launch:
-  // every candidate (three LDS tiles, the wave kernel) is prepared and timed
+  // every candidate (four LDS tiles, the wave kernel; the three smaller
+  // tiles for FP8 operands) is prepared and timed
   // on the launch itself (one warm-up and one timed run; the launch's outputs
   // are scratch that the caller clears or overwrites before real use), and
   // the fastest kept.  Choices are cached per launch class -- operand and
@@ -2079,7 +2353,8 @@ class HipExec : public Executor {
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
-    for (int cfg = 1; cfg <= (f8 ? 3 : 4); ++cfg) {
+    const bool no_pipe = std::getenv("DMRG_PIPE") && std::atoi(std::getenv("DMRG_PIPE")) == 0;
+    for (int cfg = 1; cfg <= (f8 ? 3 : no_pipe ? 5 : 9); ++cfg) {
       void* h = prepare_cfg(jobs, terms, da, db, dc, cfg);
       if (!((Prepared*)h)->padded) {  // not a padded launch after all: no choice to make
         HIP_OK(hipEventDestroy(e0));
@@ -2115,12 +2390,15 @@ class HipExec : public Executor {
   }
   std::string tuner_report() const override {
     std::lock_guard<std::mutex> lock(tune_mu());
-    int cnt[5] = {0, 0, 0, 0, 0};
-    for (auto& kv : tune_map()) cnt[std::max(0, std::min(4, kv.second))]++;
-    char b[256];
+    int cnt[10] = {0};
+    for (auto& kv : tune_map()) cnt[std::max(0, std::min(9, kv.second))]++;
+    char b[384];
     std::snprintf(b, sizeof b,
-                  "{\"classes\": %zu, \"timed_here\": %d, \"64x64\": %d, \"64x128\": %d, \"128x64\": %d, \"wave32x32\": %d}",
-                  tune_map().size(), tuned_count(), cnt[1], cnt[2], cnt[3], cnt[4]);
+                  "{\"classes\": %zu, \"timed_here\": %d, \"64x64\": %d, \"64x128\": %d, \"128x64\": %d, "
+                  "\"wave32x32\": %d, \"128x128\": %d, \"pipe64x64\": %d, \"pipe64x128\": %d, "
+                  "\"pipe128x64\": %d, \"pipe128x128\": %d}",
+                  tune_map().size(), tuned_count(), cnt[1], cnt[2], cnt[3], cnt[4], cnt[5], cnt[6], cnt[7], cnt[8],
+                  cnt[9]);
     return b;
   }
   void* prepare_cfg(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc,
@@ -2175,8 +2453,9 @@ class HipExec : public Executor {
                            P->d_items + t0, P->part ? P->part : part_, nt);
       }
     } else {
-      KernelFn k = P->padded ? pick_padded(P->dc, P->bm, P->bn, P->da == DT_FP8, P->db == DT_FP8)
-                             : pick(P->mode, P->da, P->db, P->dc, P->kt);
+      KernelFn k = P->pipe     ? pick_pipe(P->dc, P->bm, P->bn)
+                   : P->padded ? pick_padded(P->dc, P->bm, P->bn, P->da == DT_FP8, P->db == DT_FP8)
+                               : pick(P->mode, P->da, P->db, P->dc, P->kt);
       for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
         const long long nt = std::min(maxg, P->nitems - t0);
         hipLaunchKernelGGL(k, dim3((unsigned)nt), dim3(256), 0, stream_, P->d_jobs, P->d_terms, P->d_items + t0,
@@ -2530,7 +2809,7 @@ class HipExec : public Executor {
     char key[128];
     int cfg = 0;
     while (std::fscanf(fp, "%127s %d", key, &cfg) == 2)
-      if (cfg >= 1 && cfg <= 4) tune_map()[key] = cfg;
+      if (cfg >= 1 && cfg <= 9) tune_map()[key] = cfg;
     std::fclose(fp);
   }
   static void save_tune_file(const std::string& key, int cfg) {

@@ -71,7 +71,8 @@ def test_heff_diag_matches_oracle_dense():
 
 @pytest.mark.parametrize("prec,bound,kt", [(1, 2.0 ** -24 * 64, ""), (2, 2.0 ** -8 * 8, "32"),
                                            (2, 2.0 ** -8 * 8, "64"), (2, 2.0 ** -8 * 8, "")])
-@pytest.mark.parametrize("kernel", ["lean", "generic", "64x64", "64x128", "128x64", "wave"])
+@pytest.mark.parametrize("kernel", ["lean", "generic", "64x64", "64x128", "128x64", "128x128", "pipe64x64",
+                                    "pipe64x128", "pipe128x64", "pipe128x128", "wave"])
 def test_hpsi_low_precision_error_bound(prec, bound, kt, kernel, monkeypatch):
     # BF16 H*psi launches run on the lean padded-operand kernel unless it is
     # switched off; the generic kernel then runs with K slabs of 32 or 64.

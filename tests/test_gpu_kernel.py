@@ -100,7 +100,8 @@ def test_gemm_bf16_lean_and_generic_kernels_agree(m, n, k, monkeypatch):
     assert np.abs(wave - generic).max() <= 1e-5 * np.abs(generic).max()
 
 
-@pytest.mark.parametrize("tile", ["64x64", "64x128", "128x64"])
+@pytest.mark.parametrize("tile", ["64x64", "64x128", "128x64", "128x128", "pipe64x64", "pipe64x128", "pipe128x64",
+                                  "pipe128x128"])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (65, 63, 17), (130, 70, 300), (7, 200, 129), (200, 9, 5), (129, 257, 40)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_bf16_lean_tile_shapes(tile, m, n, k, ta, tb, monkeypatch):
