@@ -883,8 +883,9 @@ __device__ __forceinline__ void pipe_wait_barrier() {
 //   * stored along k (A not transposed, B transposed): R rows of 32 k in
 //     four 16-byte chunks, chunk q of row r at slot q ^ ((r >> 2) & 3);
 //   * stored along m or n: 32 k rows of R elements in R / 8 chunks, chunk q
-//     of k row k at slot q ^ ((k >> 3) & (R / 8 - 1)) (conflict-free
-//     reads of the four k groups of an MFMA operand).
+//     of k row k at slot q ^ ((k >> 3) & (R / 8 - 1)) (the four k groups of
+//     an MFMA operand in different banks), read with the gfx950 transposing
+//     LDS read.
 // Each wave copies R / 64 consecutive 1 KB pieces of each operand slab.
 // Lanes outside the operand (rows past m or n, k chunks past K) copy the
 // operand's first 16 bytes instead, so every wave issues the same number of
@@ -999,6 +1000,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 8
   // LDS element offsets of this lane's MFMA operands (k group lg)
   auto offK = [&](int r) { return r * KT + 8 * (lg ^ ((r >> 2) & 3)); };
   auto offMN = [&](int R, int k, int r) { return k * R + 8 * ((r >> 3) ^ ((k >> 3) & (R / 8 - 1))) + (r & 7); };
+  // Operand stored along m / n: ds_read_b64_tr_b16 over each group of 16
+  // lanes returns to lane i the value j of the 4-element run addressed by
+  // lane 4 j + (i >> 2), element i & 3.  Lane q of k group lg addresses the
+  // run at k row 8 lg + (q >> 2) (+ 4 for the upper half) and column
+  // c0 + 4 (q & 3), so lane (lr, lg) receives column c0 + lr at k rows
+  // 8 lg .. 8 lg + 7: its MFMA operand, in two reads instead of eight.
+  typedef short s4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(3))) s4 lds_s4;
+  auto frag_mn = [&](const u16* sX, int R, int c0) -> bf8 {
+    const int k1 = 8 * lg + (lr >> 2), c = c0 + 4 * (lr & 3);
+    const s4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(sX + offMN(R, k1, c)));
+    const s4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(sX + offMN(R, k1 + 4, c)));
+    return __builtin_bit_cast(bf8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+  };
   int i = 0;
   while (tc < W.tend) {
     const int st = i % S;
@@ -1024,26 +1039,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 8
 #pragma unroll
     for (int a = 0; a < FA; ++a) {
       const int r = wm + a * 16 + lr;
-      if (caK) {
-        av[a] = *(const bf8*)(sA + offK(r));
-      } else {
-        u16 e[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) e[j] = sA[offMN(BM, 8 * lg + j, r)];
-        av[a] = __builtin_bit_cast(bf8, e);
-      }
+      if (caK) av[a] = *(const bf8*)(sA + offK(r));
+      else av[a] = frag_mn(sA, BM, wm + a * 16);
     }
 #pragma unroll
     for (int b = 0; b < FB; ++b) {
       const int r = wn + b * 16 + lr;
-      if (cbK) {
-        bv[b] = *(const bf8*)(sB + offK(r));
-      } else {
-        u16 e[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) e[j] = sB[offMN(BN, 8 * lg + j, r)];
-        bv[b] = __builtin_bit_cast(bf8, e);
-      }
+      if (cbK) bv[b] = *(const bf8*)(sB + offK(r));
+      else bv[b] = frag_mn(sB, BN, wn + b * 16);
     }
     const int nvk = cK - kc - 8 * lg;  // valid k of this lane's eight
     if (nvk < 8) {

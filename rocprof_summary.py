@@ -16,7 +16,7 @@ H*psi (bench.py times one BF16 and one FP64 H*psi per step).
 `bench.py --copy-calibration MIB`.  Each counter is scaled by what it reads
 for the plain device copy of known size (bytes copied / counter bytes), and
 the HBM bytes of the dominant kernels -- the BF16 grouped GEMMs
-gemm_bf16_padded and gemm_bf16_wave -- over the last BF16 H*psi of the run
+gemm_bf16_pipe, gemm_bf16_padded and gemm_bf16_wave -- over the last BF16 H*psi of the run
 (its last HPSI_LAUNCHES dispatches of them) are written to OUT.json together
 with the SHA-256 of the kernel source, so that a later reader can tell whether
 the figures still describe the kernel.
@@ -39,11 +39,12 @@ def source_sha256() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-BF16_GEMMS = ("gemm_bf16_padded", "gemm_bf16_wave")
+BF16_GEMMS = ("gemm_bf16_padded", "gemm_bf16_wave", "gemm_bf16_pipe")
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"(gemm_kernel|gemm_bf16_padded|gemm_bf16_wave|gemm_f64_wave|reduce_kernel|convert_kernel|pack_kernel)"
+    m = re.search(r"(gemm_kernel|gemm_bf16_padded|gemm_bf16_pipe|gemm_bf16_wave|gemm_f64_wave|reduce_kernel|convert_kernel|"
+                  r"pack_kernel)"
                   r"<([^>]*)>", name)
     if m:
         return f"{m.group(1)}<{m.group(2)}>"
@@ -66,7 +67,7 @@ def trace(d: str) -> None:
     print("| kernel | calls | total ms | avg us |\n|---|---|---|---|")
     for k, (n, ms) in sorted(tot.items(), key=lambda x: -x[1][1])[:12]:
         print(f"| {k} | {n} | {ms:.1f} | {ms / n * 1e3:.1f} |")
-    # last BF16 H*psi: the final run of consecutive gemm_bf16_padded / reduce launches
+    # last BF16 H*psi: the final run of consecutive BF16 grouped GEMM / reduce launches
     names = [short_name(r["Kernel_Name"]) for r in rows]
     last = max(i for i, n in enumerate(names) if n.startswith(BF16_GEMMS))
     first = last
