@@ -232,6 +232,11 @@ def main():
                     help="cap on the X intermediates of one H*psi chunk (elements; 0: library default)")
     ap.add_argument("--sweep-steps", type=int, default=0,
                     help="--sweep: time only the first N blocks (keeps only the operator blocks they need)")
+    ap.add_argument("--full-sweeps", type=int, default=0, metavar="N",
+                    help="N full sweeps over the whole chain after a warm-up half-sweep (operator blocks of every "
+                         "bond kept; CAS(32,32) D=1024 fits one GPU)")
+    ap.add_argument("--bulk", default="bf16", choices=["fp64", "fp32", "bf16"],
+                    help="--full-sweeps: Davidson bulk matvec precision (fp32 / bf16 end with FP64 refinement)")
     ap.add_argument("--sweep", action="store_true",
                     help="time a half-sweep from the centre to the right end (operator blocks of every bond "
                          "kept; fits one GPU for CAS(32,32) D=1024, not for CAS(82,82) D=4096)")
@@ -245,6 +250,9 @@ def main():
         sys.exit(2)
     if args.config == "batch48":
         batch_main(args)
+        return
+    if args.full_sweeps > 0:
+        full_sweeps_main(args)
         return
     if args.sweep:
         sweep_main(args)
@@ -438,9 +446,10 @@ def sweep_main(args):
     psi, _ = random_psi(mps, seed=w["seed"] + 1)
     total_blocks = w["n"] - 1 - w["k"]  # blocks (k, k+1) .. (n-2, n-1)
     steps_max = args.sweep_steps if args.sweep_steps > 0 else total_blocks
-    keep = 1 if steps_max >= total_blocks else max(2, steps_max + 1)
+    keep = 1 if steps_max >= total_blocks else max(2, steps_max)
     dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=BF16, davidson_max_iter=400,
-              davidson_jd_inner=args.jd_inner, keep_blocks=keep, next_guess=True)
+              davidson_max_subspace=48, work_budget_elems=args.x_budget, davidson_jd_inner=args.jd_inner,
+              keep_blocks=keep, next_guess=True)
     bs, cnt = mps.bond_table()
     t0 = time.perf_counter()
     dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())
@@ -484,6 +493,82 @@ def sweep_main(args):
                     f"first {done} of {total_blocks} blocks; value = their mean time x {total_blocks} (extrapolated)",
         "timed_seconds": t_sweep,
         "all_converged": all(st["converged"] for st in steps),
+        "setup_s": {"operator_blocks": t_env},
+        "sweep_steps": steps,
+    }
+    print(json.dumps(out), flush=True)
+    dm.close()
+
+
+def full_sweeps_main(args):
+    """--full-sweeps N: N full sweeps of two-site DMRG over the whole chain
+    (Sec. "Numerical procedure"), after a warm-up half-sweep from the centre
+    to the right end: every block solved by Davidson to the residual 1e-7 in
+    the bulk precision --bulk (fp64: FP64 matvecs only; fp32 / bf16: that
+    precision then FP64 refinement), truncated to D multiplets, the operator
+    block grown across the new bond.  Right-moving steps start from the
+    state the truncation carries over (dmrg_next_guess), left-moving ones
+    from a random vector.  The operator blocks of every bond are kept
+    (keep_blocks 1).  Prints one JSON line with the energy at the end of
+    every sweep, the lowest energy, matvec counts and times."""
+    import numpy as np
+    import torch
+    from paper_2503_20700_amd.binding import BF16, DMRG, FP32, FP64
+    from synth.mps import random_mps, random_psi
+
+    prec = {"fp64": FP64, "fp32": FP32, "bf16": BF16}[args.bulk]
+    w = workload(args.config)
+    n, k0 = w["n"], w["k"]
+    mps = random_mps(n, w["N"], w["two_s"], w["D"], k=k0, seed=w["seed"])
+    psi, _ = random_psi(mps, seed=w["seed"] + 1)
+    dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=prec, davidson_max_iter=600, davidson_max_subspace=48,
+              work_budget_elems=args.x_budget, davidson_jd_inner=args.jd_inner, keep_blocks=True, next_guess=True)
+    bs, cnt = mps.bond_table()
+    t0 = time.perf_counter()
+    dm.set_mps(k0, bs, cnt, mps.site_blocks_flat())
+    t_env = time.perf_counter() - t0
+    log(f"{w['name']}: operator blocks of every bond built in {t_env:.1f}s; bulk precision {args.bulk}")
+    plan = [("warm-up", 1)] * (n - 2 - k0)
+    for sw in range(args.full_sweeps):
+        plan += [(f"sweep {sw + 1}", -1)] * (n - 2) + [(f"sweep {sw + 1}", 1)] * (n - 2)
+    steps, ends = [], {}
+    start = psi
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i, (label, direction) in enumerate(plan):
+        k = dm.k
+        t1 = time.perf_counter()
+        r = dm.davidson(start)
+        t2 = time.perf_counter()
+        err, kept = dm.truncate(r["psi"], w["D"], 0.0, direction)
+        t3 = time.perf_counter()
+        steps.append({"sweep": label, "block": [k, k + 1], "direction": direction, "davidson_s": t2 - t1,
+                      "truncate_and_grow_s": t3 - t2, "energy_Eh": r["energy"], "residual": r["resid"],
+                      "converged": r["converged"], "matvecs": {"lowprec": r["n_lo"], "fp64": r["n_fp64"]},
+                      "trunc_err": err, "d_kept": kept})
+        ends[label] = r["energy"]
+        log(f"{label} block ({k},{k + 1}) dir {direction:+d}: {t3 - t1:.1f}s, E {r['energy']:.10f}, "
+            f"residual {r['resid']:.1e}, matvecs {r['n_lo']}+{r['n_fp64']}")
+        nxt = plan[i + 1][1] if i + 1 < len(plan) else None
+        _, nel = dm.psi_layout()
+        start = dm.next_guess() if (direction > 0 and nxt == 1) else np.zeros(nel)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_start
+    n_lo = sum(st["matvecs"]["lowprec"] for st in steps)
+    n_hi = sum(st["matvecs"]["fp64"] for st in steps)
+    out = {
+        "metric": f"{args.full_sweeps} full sweeps (+ warm-up half-sweep), " + w["name"],
+        "value": t_all, "unit": "s", "n_gpus": 1, "steps": len(steps), "warmup": 0,
+        "ms_per_step": t_all / max(len(steps), 1) * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.bulk, "data": "synthetic",
+        "config": {"workload": w["name"], "n_orb": n, "D": w["D"], "first_block": [k0, k0 + 1],
+                   "bulk_precision": args.bulk, "refinement": "FP64" if args.bulk != "fp64" else None,
+                   "davidson": {"residual_target": 1e-7, "max_iter": 600, "max_subspace": 48,
+                                "jd_inner_cg": args.jd_inner}},
+        "energy_at_sweep_end_Eh": ends,
+        "lowest_energy_Eh": min(st["energy_Eh"] for st in steps),
+        "all_converged": all(st["converged"] for st in steps),
+        "matvecs": {"lowprec": n_lo, "fp64": n_hi},
         "setup_s": {"operator_blocks": t_env},
         "sweep_steps": steps,
     }
