@@ -506,12 +506,11 @@ def full_sweeps_main(args):
     to the right end: every block solved by Davidson to the residual 1e-7 in
     the bulk precision --bulk (fp64: FP64 matvecs only; fp32 / bf16: that
     precision then FP64 refinement), truncated to D multiplets, the operator
-    block grown across the new bond.  Right-moving steps start from the
-    state the truncation carries over (dmrg_next_guess), left-moving ones
-    from a random vector.  The operator blocks of every bond are kept
+    block grown across the new bond.  Every block after the first starts
+    from the state the truncation carried over (dmrg_next_guess, both
+    directions).  The operator blocks of every bond are kept
     (keep_blocks 1).  Prints one JSON line with the energy at the end of
     every sweep, the lowest energy, matvec counts and times."""
-    import numpy as np
     import torch
     from paper_2503_20700_amd.binding import BF16, DMRG, FP32, FP64
     from synth.mps import random_mps, random_psi
@@ -549,9 +548,8 @@ def full_sweeps_main(args):
         ends[label] = r["energy"]
         log(f"{label} block ({k},{k + 1}) dir {direction:+d}: {t3 - t1:.1f}s, E {r['energy']:.10f}, "
             f"residual {r['resid']:.1e}, matvecs {r['n_lo']}+{r['n_fp64']}")
-        nxt = plan[i + 1][1] if i + 1 < len(plan) else None
-        _, nel = dm.psi_layout()
-        start = dm.next_guess() if (direction > 0 and nxt == 1) else np.zeros(nel)
+        if i + 1 < len(plan):
+            start = dm.next_guess()  # carried across the cut the truncation just moved over
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t_start
     n_lo = sum(st["matvecs"]["lowprec"] for st in steps)

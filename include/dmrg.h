@@ -98,9 +98,9 @@ typedef struct {
                                   host overhead for small blocks); re-recorded when
                                   the library's scratch moves; not used while
                                   dmrg_kernel_timing records                       */
-  int next_guess;              /* 1: dmrg_truncate moving right (+1) also forms the
-                                  start vector of the block it moves to (read it
-                                  with dmrg_next_guess)                            */
+  int next_guess;              /* 1: dmrg_truncate (either direction) also forms
+                                  the start vector of the block it moves to (read
+                                  it with dmrg_next_guess)                         */
   long long hbm_budget_bytes;  /* cap on the device memory the context's buffers
                                   hold (operator blocks and their low-precision
                                   copies, H*psi intermediates, Davidson vectors);
@@ -224,10 +224,11 @@ int dmrg_truncate_dbss(dmrg_ctx *c, int k, const double *psi, int direction, int
                        double eps_tr, double *trunc_err, int *d_kept);
 
 /* Start vector for the current block (k, k+1) carried over by the last
- * dmrg_truncate(direction +1) with opts.next_guess set (Sec. "Numerical
- * procedure": each sweep step starts from the previous step's wavefunction):
- * the kept part of the previous psi, contracted with the right-canonical
- * tensor of site k+1 and recoupled to this block's middle-cut basis (one 6j
+ * dmrg_truncate with opts.next_guess set (Sec. "Numerical procedure": each
+ * sweep step starts from the previous step's wavefunction): the kept part of
+ * the previous psi, contracted with the right-canonical tensor of site k+1
+ * (after a move to the right) or the left-canonical tensor of site k (after
+ * a move to the left) and recoupled to this block's middle-cut basis (one 6j
  * per block).  Without truncation it is the same state; its norm squared is
  * 1 - trunc_err for a normalised psi.  psi: n_elems host values (the layout of
  * dmrg_psi_layout).  Errors: ARG if no vector was carried to this block,

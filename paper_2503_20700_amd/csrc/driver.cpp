@@ -584,6 +584,95 @@ static void next_block_guess(dmrg_ctx* c, int k, const PsiLayout& lay, const dou
   c->guess_k = k + 1;
 }
 
+// Start vector for the two-site block (k-1, k) after a truncation at
+// (k, k+1) that moves left: the kept part of psi, psi V (V: the kept
+// eigenvectors of the right density matrix, i.e. the new right-canonical
+// tensor of site k+1 transposed), contracted with the left-canonical tensor
+// of site k-1 and recoupled from ((l s_k) S_a, c') S to (l, (s_k c') S_c) S
+// by one 6j per block -- the mirror of next_block_guess; no fermion sign
+// enters since the site order is unchanged.
+static void prev_block_guess(dmrg_ctx* c, int k, const PsiLayout& lay, const double* psi,
+                             const std::vector<CutSector>& secs, const std::vector<std::vector<int>>& kept,
+                             const std::vector<int>& new_of, const std::vector<double>& hV, const Bond& nb) {
+  Context& C = *c->C;
+  const SiteTensor& A = C.sites[k - 1];
+  if (!A.left || A.buf < 0) return;
+  int64_t nav = 0;
+  for (auto& bk : A.blocks) nav = std::max<int64_t>(nav, bk.off + (int64_t)bk.rows * bk.cols);
+  std::vector<double> av((size_t)std::max<int64_t>(nav, 1));
+  if (nav) c->ex->download(av.data(), C.ptr(A.buf), (size_t)nav * 8);
+  // Cm = psi V per old super-block whose right sector keeps states (rows x kept)
+  std::map<std::pair<int, int>, int> sec_index;
+  for (size_t si = 0; si < secs.size(); ++si) sec_index[{secs[si].n, secs[si].s2}] = (int)si;
+  std::vector<std::vector<double>> Cm(lay.sbs.size());
+  std::vector<int> cut_of(lay.sbs.size(), -1);
+  for (size_t sbi = 0; sbi < lay.sbs.size(); ++sbi) {
+    const auto& sb = lay.sbs[sbi];
+    const int si = sec_index.at({sb.cn, sb.cs2});
+    if (new_of[si] < 0) continue;
+    cut_of[sbi] = si;
+    const int da = (int)kept[si].size(), dim = secs[si].dim;
+    std::vector<double>& m = Cm[sbi];
+    m.assign((size_t)sb.nrows * da, 0.0);
+    for (int r = 0; r < sb.nrows; ++r) {
+      const double* prow = psi + sb.off + (int64_t)r * sb.ncols;
+      for (int q = 0; q < da; ++q) {
+        double acc = 0.0;
+        for (int col = 0; col < sb.ncols; ++col) acc += prow[col] * hV[(size_t)secs[si].off + (size_t)col * dim + kept[si][q]];
+        m[(size_t)r * da + q] = acc;
+      }
+    }
+  }
+  const Bond& bl = C.bonds[k - 1];
+  const Bond& bk = C.bonds[k];
+  PsiLayout nl;
+  nl.build(bl, nb, c->opts.n_elec, c->opts.two_s);
+  std::vector<double> g((size_t)nl.size, 0.0);
+  const int S = c->opts.two_s;
+  auto loc2s = [](int sig) { return sig == 1 ? 1 : 0; };
+  for (const auto& sb2 : nl.sbs) {
+    for (const auto& rr : sb2.rows) {  // l'' = bond k-1 sector rr.il, sigma_{k-1} = rr.s1
+      for (size_t il = 0; il < bk.secs.size(); ++il) {
+        const Sector& ls = bk.secs[il];  // l: (l'' sigma_{k-1}) coupled to the new left sector
+        if (ls.n != sb2.an || ls.s2 != sb2.as2) continue;
+        auto ait = A.find.find({rr.il, rr.s1, (int)il});
+        if (ait == A.find.end()) continue;
+        const auto& ab = A.blocks[ait->second];  // D_l'' x D_l
+        for (const auto& cc : sb2.cols) {  // sigma_k = cc.s2, c' = new bond k+1 sector cc.ir
+          for (size_t sbi = 0; sbi < lay.sbs.size(); ++sbi) {
+            const int si = cut_of[sbi];
+            if (si < 0 || new_of[si] != cc.ir) continue;
+            const auto& sb = lay.sbs[sbi];
+            int r0o = -1;
+            for (const auto& ro : sb.rows)
+              if (ro.il == (int)il && ro.s1 == cc.s2) r0o = ro.r0;
+            if (r0o < 0) continue;
+            const int da = (int)kept[si].size();
+            if (da != cc.dr) throw std::runtime_error("prev_block_guess: kept states do not match the new bond");
+            // <(l, (sigma_k c') S_c) S | ((l sigma_k) S_a, c') S>
+            const int j1 = ls.s2, j2 = loc2s(cc.s2), j3 = nb.secs[cc.ir].s2, J12 = sb.as2, J23 = sb2.cs2;
+            const int ph = (j1 + j2 + j3 + S) / 2;
+            const double w = ((ph & 1) ? -1.0 : 1.0) * std::sqrt((J12 + 1.0) * (J23 + 1.0)) *
+                             sixj2(j1, j2, J12, j3, S, J23);
+            if (w == 0.0) continue;
+            for (int i = 0; i < rr.dl; ++i) {
+              double* grow = g.data() + sb2.off + (int64_t)(rr.r0 + i) * sb2.ncols + cc.c0;
+              for (int t = 0; t < ab.cols; ++t) {
+                const double at = w * av[(size_t)ab.off + (size_t)i * ab.cols + t];
+                if (at == 0.0) continue;
+                const double* crow = Cm[sbi].data() + (size_t)(r0o + t) * da;
+                for (int j = 0; j < da; ++j) grow[j] += at * crow[j];
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  c->guess.swap(g);
+  c->guess_k = k - 1;
+}
+
 extern "C" int dmrg_truncate(dmrg_ctx* c, int k, const double* psi, int dir, int d_max, double eps_tr,
                              double* trunc_err, int* d_kept) {
   return dmrg_truncate_dbss(c, k, psi, dir, 0, d_max, eps_tr, trunc_err, d_kept);
@@ -847,6 +936,9 @@ static int truncate_core(dmrg_ctx* c, int k, const double* psi, int dir, int d_m
     if (dir > 0 && c->opts.next_guess && k + 3 <= C.n) {
       next_block_guess(c, k, lay, psi, secs, kept, new_of, hV, nb);
       lap("next-block start vector");
+    } else if (dir < 0 && c->opts.next_guess && k >= 1) {
+      prev_block_guess(c, k, lay, psi, secs, kept, new_of, hV, nb);
+      lap("previous-block start vector");
     }
     // ---- grow the operator block across the cut, move the two-site block if possible
     c->reset_plan();

@@ -893,7 +893,8 @@ __device__ __forceinline__ void pipe_wait_barrier() {
 // reach rows and columns that are not written back (past m or n), or are
 // zeroed in registers (k past K) before the MFMA.
 template <int DC, int BM, int BN, int S>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 8192 ? 2 : (BM * BN > 4096 ? 3 : 5)))) void gemm_bf16_pipe(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    S == 2 ? (BM * BN > 4096 ? 5 : 7) : (BM * BN > 8192 ? 2 : (BM * BN > 4096 ? 3 : 5))))) void gemm_bf16_pipe(
     const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms, const WorkItem* __restrict__ items,
     void* __restrict__ part) {
   constexpr int KT = 32;
@@ -1078,6 +1079,216 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM * BN > 8
       for (int b = 0; b < FB; ++b) acc[a][b] *= scale;
   }
   tile_store<DC, BM, BN>(acc, W, J, smem, part, m0, n0, wm, wn, lr, lg, tid);
+}
+
+// FP64 counterpart of gemm_bf16_pipe for padded launches: slabs of 16 k
+// (16-byte LDS DMA pieces of two doubles), S stages, v_mfma_f64_16x16x4f64
+// with 2 x 2 blocks per wave (64 x 64 tile) or 4 x 2 / 2 x 4 (128 x 64,
+// 64 x 128).  MFMA step s of a slab takes k = 4 lg + s from lane group lg,
+// so a lane's four k values of an operand stored along k are one 32-byte
+// run.  LDS layouts per stage and operand (R rows):
+//   * along k: R rows of 16 doubles in eight 16-byte chunks, chunk q of row r
+//     at slot q ^ (r & 7), read as two 16-byte vectors;
+//   * along m or n: 16 k rows of R doubles in R / 2 chunks, chunk q of k row
+//     k at slot q ^ (((k >> 2) & 3) << 3), read as four 8-byte values.
+// Product weights multiply A as it is read from LDS (as in gemm_kernel).
+// Same copy / wait / masking rules as gemm_bf16_pipe.
+template <int BM, int BN, int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(S == 2 ? 4 : 3))) void gemm_f64_pipe(
+    const RawJob* __restrict__ jobs, const RawTerm* __restrict__ terms, const WorkItem* __restrict__ items,
+    void* __restrict__ part) {
+  constexpr int KT = 16;
+  constexpr int FA = BM / 32, FB = BN / 32;
+  constexpr int NA = BM / 32, NB = BN / 32;  // 1 KB copies per wave per slab (R / 8 pieces over 4 waves)
+  constexpr int NI = NA + NB;
+  constexpr int SA = BM * KT, STG = (BM + BN) * KT;  // doubles
+  static_assert(S >= 2 && S <= 3, "pipeline depth");
+  __shared__ __attribute__((aligned(16))) double smem[S * STG];
+  const int tid = threadIdx.x;
+  const WorkItem W = items[blockIdx.x];
+  const RawJob J = jobs[W.job];
+  const int m0 = W.ti * BM, n0 = W.tj * BN;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int lr = lane & 15, lg = lane >> 4;
+
+  d4 acc[FA][FB];
+#pragma unroll
+  for (int a = 0; a < FA; ++a)
+#pragma unroll
+    for (int b = 0; b < FB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  if (W.has_ident)
+    for (int t = W.tbeg; t < W.tend; ++t) {
+      const int fl = terms[t].flags;
+      if (!(fl & (TF_IDENT_A | TF_IDENT_B))) continue;
+      const RawTerm T = terms[t];
+      const bool ia = fl & TF_IDENT_A;
+      const double* P = (const double*)(ia ? T.B : T.A);
+      const long long ld = ia ? T.ldb : T.lda;
+      const bool tr = ia ? (fl & TF_TRANS_B) : (fl & TF_TRANS_A);
+#pragma unroll
+      for (int a = 0; a < FA; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = m0 + wm + a * 16 + 4 * v + lg, col = n0 + wn + b * 16 + lr;
+            if (row < J.m && col < J.n) acc[a][b][v] += T.alpha * P[tr ? (long long)col * ld + row : (long long)row * ld + col];
+          }
+    }
+
+  typedef const __attribute__((address_space(4))) RawTerm CTerm;
+  CTerm* cterms = (CTerm*)(uintptr_t)terms;
+  auto next_dense = [&](int t) {
+    while (t < W.tend && ((cterms[t].flags & (TF_IDENT_A | TF_IDENT_B)) || cterms[t].k <= 0)) ++t;
+    return t;
+  };
+  const unsigned lds0 = (unsigned)(uintptr_t)smem;
+  int tl = next_dense(W.dense0), kl = 0;
+  const double* LA = nullptr;
+  const double* LB = nullptr;
+  long long lda = 0, ldb = 0;
+  int lK = 0;
+  bool laK = true, lbK = true;
+  auto load_term = [&]() {
+    CTerm& T = cterms[tl];
+    LA = (const double*)T.A;
+    LB = (const double*)T.B;
+    lda = T.lda;
+    ldb = T.ldb;
+    lK = T.k;
+    const int fl = T.flags;
+    laK = !(fl & TF_TRANS_A);
+    lbK = (fl & TF_TRANS_B);
+  };
+  if (tl < W.tend) load_term();
+  auto copy_operand = [&](const double* P, long long ld, bool alongK, int R, int r0, int ext, int nv, unsigned dst) {
+    for (int v = 0; v < nv; ++v) {
+      const int c = wave * nv + v;
+      const int pz = c * 64 + lane;
+      const double* g = P;
+      if (alongK) {
+        const int row = pz >> 3, q = (pz & 7) ^ (row & 7);
+        if (r0 + row < ext && kl + 2 * q < lK) g = P + (long long)(r0 + row) * ld + kl + 2 * q;
+      } else {
+        const int cpr = R / 2, kr = pz / cpr, q = (pz % cpr) ^ (((kr >> 2) & 3) << 3);
+        if (kl + kr < lK && r0 + 2 * q < ext) g = P + (long long)(kl + kr) * ld + r0 + 2 * q;
+      }
+      lds_dma16(g, __builtin_amdgcn_readfirstlane(dst + c * 1024));
+    }
+  };
+  auto issue = [&](int st) {
+    const unsigned base = lds0 + (unsigned)(st * STG) * 8u;
+    copy_operand(LA, lda, laK, BM, m0, J.m, NA, base);
+    copy_operand(LB, ldb, lbK, BN, n0, J.n, NB, base + SA * 8u);
+    kl += KT;
+    if (kl >= lK) {
+      tl = next_dense(tl + 1);
+      kl = 0;
+      if (tl < W.tend) load_term();
+    }
+  };
+  int issued = 0;
+#pragma unroll
+  for (int s0 = 0; s0 < S - 1; ++s0)
+    if (tl < W.tend) {
+      issue(s0);
+      ++issued;
+    }
+  int tc = next_dense(W.dense0), kc = 0, cK = 0;
+  bool caK = true, cbK = true;
+  double alpha = 1.0;
+  auto use_term = [&]() {
+    CTerm& T = cterms[tc];
+    cK = T.k;
+    const int fl = T.flags;
+    caK = !(fl & TF_TRANS_A);
+    cbK = (fl & TF_TRANS_B);
+    alpha = T.alpha;
+  };
+  if (tc < W.tend) use_term();
+  // this lane's four values (k = 4 lg + s) of row / column r
+  auto frag = [&](const double* sX, bool alongK, int R, int r, double (&f)[4]) {
+    if (alongK) {
+      const double2 u = *(const double2*)(sX + r * KT + 2 * ((2 * lg) ^ (r & 7)));
+      const double2 w = *(const double2*)(sX + r * KT + 2 * ((2 * lg + 1) ^ (r & 7)));
+      f[0] = u.x;
+      f[1] = u.y;
+      f[2] = w.x;
+      f[3] = w.y;
+    } else {
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int k = 4 * lg + s2;
+        f[s2] = sX[k * R + 2 * ((r >> 1) ^ (lg << 3)) + (r & 1)];
+      }
+    }
+  };
+  int i = 0;
+  while (tc < W.tend) {
+    const int st = i % S;
+    const int ahead = issued - i - 1;
+    if (S >= 3 && ahead >= 1) pipe_wait_barrier<NI>();
+    else pipe_wait_barrier<0>();
+    if (tl < W.tend) {
+      issue(issued % S);
+      ++issued;
+    }
+    const double* sA = smem + st * STG;
+    const double* sB = sA + SA;
+    double af[FA][4], bf[FB][4];
+#pragma unroll
+    for (int a = 0; a < FA; ++a) frag(sA, caK, BM, wm + a * 16 + lr, af[a]);
+#pragma unroll
+    for (int b = 0; b < FB; ++b) frag(sB, cbK, BN, wn + b * 16 + lr, bf[b]);
+    const int nvk = cK - kc - 4 * lg;  // valid k of this lane's four
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const bool ok = s2 < nvk;
+#pragma unroll
+      for (int a = 0; a < FA; ++a) af[a][s2] = ok ? af[a][s2] * alpha : 0.0;
+#pragma unroll
+      for (int b = 0; b < FB; ++b) bf[b][s2] = ok ? bf[b][s2] : 0.0;
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+      for (int a = 0; a < FA; ++a)
+#pragma unroll
+        for (int b = 0; b < FB; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a][s2], bf[b][s2], acc[a][b], 0, 0, 0);
+    ++i;
+    kc += KT;
+    if (kc >= cK) {
+      tc = next_dense(tc + 1);
+      kc = 0;
+      if (tc < W.tend) use_term();
+    }
+  }
+  // write back: C (FP64, rows 4 v + lg of each 16 x 16 block), or the partial slot
+  if (W.slot >= 0) {
+    double* P = (double*)part + (long long)W.slot * (BM * BN);
+#pragma unroll
+    for (int a = 0; a < FA; ++a)
+#pragma unroll
+      for (int b = 0; b < FB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) P[(wm + a * 16 + 4 * v + lg) * BN + wn + b * 16 + lr] = acc[a][b][v];
+    return;
+  }
+  double* C = (double*)J.C;
+#pragma unroll
+  for (int a = 0; a < FA; ++a)
+#pragma unroll
+    for (int b = 0; b < FB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + a * 16 + 4 * v + lg, col = n0 + wn + b * 16 + lr;
+        if (row < J.m && col < J.n) {
+          const long long o = (long long)row * J.ldc + col;
+          if (J.accumulate) C[o] += acc[a][b][v];
+          else C[o] = acc[a][b][v];
+        }
+      }
 }
 
 // BF16 kernel for padded launches dominated by small blocks (many output
@@ -1868,6 +2079,8 @@ struct Prepared {
   bool padded = false;  // BF16 launch served by gemm_bf16_padded
   bool wave = false;    // ... or by gemm_bf16_wave (32 x 32 tile per wave)
   bool pipe = false;    // ... or by gemm_bf16_pipe (LDS DMA pipeline)
+  int stages = 0;       // its LDS stages (0: the default for the tile)
+  bool pad64 = false;   // FP64 launch whose operands suit gemm_f64_pipe
   int bm = TM, bn = TN;  // output tile of the launch
   void* part = nullptr;  // partial tiles of a fixed-scratch launch (else the executor's)
   // fixed-scratch launches: task lists kept on the host until placed
@@ -1908,13 +2121,25 @@ KernelFn pick_padded(int dc, int bm, int bn, bool af8 = false, bool bf8 = false)
 
 // The LDS-pipelined kernel for a tile (BF16 operands only); the stage count
 // keeps the LDS of a work-group at 32-48 KB.
-KernelFn pick_pipe(int dc, int bm, int bn) {
-#define P_(D, M, N, S) \
-  if (dc == D && bm == M && bn == N) return gemm_bf16_pipe<D, M, N, S>;
-  P_(DT_BF16, 64, 64, 4) P_(DT_BF16, 64, 128, 3) P_(DT_BF16, 128, 64, 3) P_(DT_BF16, 128, 128, 3)
-  P_(DT_F32, 64, 64, 4) P_(DT_F32, 64, 128, 3) P_(DT_F32, 128, 64, 3) P_(DT_F32, 128, 128, 3)
+// Two stages (16-24 KB) let more work-groups share a CU, for launches whose
+// items are a few slabs long.
+KernelFn pick_pipe(int dc, int bm, int bn, int stages = 0) {
+#define P_(D, M, N, S, SS) \
+  if (dc == D && bm == M && bn == N && (stages == 0 ? SS == 0 : stages == S)) return gemm_bf16_pipe<D, M, N, S>;
+  P_(DT_BF16, 64, 64, 4, 0) P_(DT_BF16, 64, 128, 3, 0) P_(DT_BF16, 128, 64, 3, 0) P_(DT_BF16, 128, 128, 3, 0)
+  P_(DT_F32, 64, 64, 4, 0) P_(DT_F32, 64, 128, 3, 0) P_(DT_F32, 128, 64, 3, 0) P_(DT_F32, 128, 128, 3, 0)
+  P_(DT_BF16, 64, 64, 2, 1) P_(DT_BF16, 64, 128, 2, 1) P_(DT_BF16, 128, 64, 2, 1)
+  P_(DT_F32, 64, 64, 2, 1) P_(DT_F32, 64, 128, 2, 1) P_(DT_F32, 128, 64, 2, 1)
 #undef P_
   throw std::runtime_error("executor: unsupported tile shape for the pipelined kernel");
+}
+
+KernelFn pick_pipe_f64(int bm, int bn, int stages) {
+  if (bm == 64 && bn == 64 && stages == 3) return gemm_f64_pipe<64, 64, 3>;
+  if (bm == 64 && bn == 64 && stages == 2) return gemm_f64_pipe<64, 64, 2>;
+  if (bm == 128 && bn == 64 && stages == 2) return gemm_f64_pipe<128, 64, 2>;
+  if (bm == 64 && bn == 128 && stages == 2) return gemm_f64_pipe<64, 128, 2>;
+  throw std::runtime_error("executor: unsupported tile for the FP64 pipelined kernel");
 }
 
 // Output tile of a padded BF16 launch.  Candidates 64x64, 64x128 and 128x64:
@@ -2245,7 +2470,8 @@ class HipExec : public Executor {
   // cfg (padded BF16 launches only): 0 the static rule (choose_wave /
   // choose_tile), 1..3 the tiles 64x64, 64x128, 128x64, 4 the wave kernel,
   // 5 the tile 128x128, 6..9 the LDS-pipelined kernel with tiles 64x64,
-  // 64x128, 128x64, 128x128 (5..9: BF16 operands only).
+  // 64x128, 128x64, 128x128, 10..12 the same with two stages and tiles
+  // 64x64, 64x128, 128x64 (5..12: BF16 operands only).
   Prepared* configure(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc,
                       std::vector<WorkItem>& items, std::vector<RedItem>& reds, int cfg = 0) {
     auto* P = new Prepared();
@@ -2278,6 +2504,29 @@ class HipExec : public Executor {
       if (ok && wmax > 0.0 && wmax > 1e30 * wmin) ok = false;
       P->padded = ok && (f8 || !std::getenv("DMRG_NO_PADDED_KERNEL"));
     }
+    if (P->mode == DT_F64 && db == DT_F64 && dc == DT_F64) {
+      // 16-byte LDS DMA pieces: padded rows, 16-byte aligned, even strides
+      bool ok = true;
+      for (const RawTerm& T : terms) {
+        if (T.flags & (TF_IDENT_A | TF_IDENT_B)) continue;
+        if (!(T.flags & TF_PAD_A) || !(T.flags & TF_PAD_B) || ((uintptr_t)T.A & 15) || ((uintptr_t)T.B & 15) ||
+            (T.lda & 1) || (T.ldb & 1)) {
+          ok = false;
+          break;
+        }
+      }
+      P->pad64 = ok;
+      if (ok && cfg == 0) {  // forced from the environment (tests, experiments)
+        const char* e = std::getenv("DMRG_TILE");
+        if (e && std::string(e).rfind("f64pipe", 0) == 0) {
+          const std::string t(e + 7);
+          cfg = t == "64x64" ? 20 : t == "2s64x64" ? 21 : t == "2s128x64" ? 22 : t == "2s64x128" ? 23 : 0;
+          if (!cfg)
+            throw std::runtime_error("executor: DMRG_TILE=f64pipeMxN takes 64x64, 2s64x64, 2s128x64 or 2s64x128");
+        }
+      }
+    }
+    if (cfg >= 20 && !P->pad64) cfg = 0;
     if (f8 && !P->padded) {
       delete P;
       throw std::runtime_error(
@@ -2288,16 +2537,26 @@ class HipExec : public Executor {
       const char* e = std::getenv("DMRG_TILE");
       if (e && std::string(e).rfind("pipe", 0) == 0) {
         const std::string t(e + 4);
-        cfg = t == "64x64" ? 6 : t == "64x128" ? 7 : t == "128x64" ? 8 : t == "128x128" ? 9 : 0;
-        if (!cfg) throw std::runtime_error("executor: DMRG_TILE=pipeMxN takes 64x64, 64x128, 128x64 or 128x128");
+        cfg = t == "64x64" ? 6 : t == "64x128" ? 7 : t == "128x64" ? 8 : t == "128x128" ? 9 : t == "2s64x64" ? 10
+            : t == "2s64x128" ? 11 : t == "2s128x64" ? 12 : 0;
+        if (!cfg)
+          throw std::runtime_error(
+              "executor: DMRG_TILE=pipeMxN takes 64x64, 64x128, 128x64, 128x128 (or 2sMxN: two stages)");
       }
     }
     P->kt = P->padded ? 32 : (P->mode == DT_BF16 ? choose_kt_bf16(jobs, terms) : 16);
-    if (P->padded && cfg > 0) {
-      static const int tiles[9][2] = {{64, 64}, {64, 128}, {128, 64}, {32, 32}, {128, 128},
-                                      {64, 64}, {64, 128}, {128, 64}, {128, 128}};
+    if (cfg >= 20) {  // FP64 pipelined tiles: 64x64 (3 stages), 64x64, 128x64, 64x128 (2 stages)
+      static const int t64[4][3] = {{64, 64, 3}, {64, 64, 2}, {128, 64, 2}, {64, 128, 2}};
+      P->pipe = true;
+      P->bm = t64[cfg - 20][0];
+      P->bn = t64[cfg - 20][1];
+      P->stages = t64[cfg - 20][2];
+    } else if (P->padded && cfg > 0) {
+      static const int tiles[12][2] = {{64, 64}, {64, 128}, {128, 64}, {32, 32}, {128, 128}, {64, 64},
+                                       {64, 128}, {128, 64}, {128, 128}, {64, 64}, {64, 128}, {128, 64}};
       P->wave = cfg == 4;
       P->pipe = cfg >= 6;
+      P->stages = cfg >= 10 ? 2 : 0;
       P->bm = tiles[cfg - 1][0];
       P->bn = tiles[cfg - 1][1];
     } else if (P->padded) {
@@ -2340,11 +2599,20 @@ class HipExec : public Executor {
   void* prepare_tuned(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db,
                       int dc) override {
     const bool f8 = da == DT_FP8 || db == DT_FP8;
-    if ((da != DT_BF16 && da != DT_FP8) || (db != DT_BF16 && db != DT_FP8) || (dc != DT_BF16 && dc != DT_F32) ||
-        jobs.empty() ||
-        (std::getenv("DMRG_TUNE") && std::atoi(std::getenv("DMRG_TUNE")) == 0) || std::getenv("DMRG_TILE") ||
-        std::getenv("DMRG_WAVE") || std::getenv("DMRG_NO_PADDED_KERNEL"))
+    const bool lowp = (da == DT_BF16 || da == DT_FP8) && (db == DT_BF16 || db == DT_FP8) &&
+                      (dc == DT_BF16 || dc == DT_F32);
+    const bool f64 = da == DT_F64 && db == DT_F64 && dc == DT_F64;
+    const bool no_pipe = std::getenv("DMRG_PIPE") && std::atoi(std::getenv("DMRG_PIPE")) == 0;
+    if ((!lowp && !f64) || jobs.empty() || (std::getenv("DMRG_TUNE") && std::atoi(std::getenv("DMRG_TUNE")) == 0) ||
+        std::getenv("DMRG_TILE") || std::getenv("DMRG_WAVE") || std::getenv("DMRG_NO_PADDED_KERNEL") ||
+        (f64 && (no_pipe || std::getenv("DMRG_NO_F64_WAVE"))))
       return prepare(jobs, terms, da, db, dc);
+    // candidates: BF16 / FP8 padded launches 1..12 (FP8 1..3); FP64 launches
+    // the static rule (gemm_kernel or gemm_f64_wave) and the pipelined tiles
+    std::vector<int> cands;
+    if (f64) cands = {0, 20, 21, 22, 23};
+    else
+      for (int c = 1; c <= (f8 ? 3 : no_pipe ? 5 : 12); ++c) cands.push_back(c);
     const std::string key = tune_key(jobs, terms, da, db, dc);
     std::lock_guard<std::mutex> lock(tune_mu());
     load_tune_file();
@@ -2356,10 +2624,9 @@ class HipExec : public Executor {
     hipEvent_t e0, e1;
     HIP_OK(hipEventCreate(&e0));
     HIP_OK(hipEventCreate(&e1));
-    const bool no_pipe = std::getenv("DMRG_PIPE") && std::atoi(std::getenv("DMRG_PIPE")) == 0;
-    for (int cfg = 1; cfg <= (f8 ? 3 : no_pipe ? 5 : 9); ++cfg) {
+    for (int cfg : cands) {
       void* h = prepare_cfg(jobs, terms, da, db, dc, cfg);
-      if (!((Prepared*)h)->padded) {  // not a padded launch after all: no choice to make
+      if (!(f64 ? ((Prepared*)h)->pad64 : ((Prepared*)h)->padded)) {  // no choice to make
         HIP_OK(hipEventDestroy(e0));
         HIP_OK(hipEventDestroy(e1));
         if (keep) drop(keep);
@@ -2393,15 +2660,17 @@ class HipExec : public Executor {
   }
   std::string tuner_report() const override {
     std::lock_guard<std::mutex> lock(tune_mu());
-    int cnt[10] = {0};
-    for (auto& kv : tune_map()) cnt[std::max(0, std::min(9, kv.second))]++;
-    char b[384];
-    std::snprintf(b, sizeof b,
-                  "{\"classes\": %zu, \"timed_here\": %d, \"64x64\": %d, \"64x128\": %d, \"128x64\": %d, "
-                  "\"wave32x32\": %d, \"128x128\": %d, \"pipe64x64\": %d, \"pipe64x128\": %d, "
-                  "\"pipe128x64\": %d, \"pipe128x128\": %d}",
-                  tune_map().size(), tuned_count(), cnt[1], cnt[2], cnt[3], cnt[4], cnt[5], cnt[6], cnt[7], cnt[8],
-                  cnt[9]);
+    static const std::pair<int, const char*> names[] = {
+        {1, "64x64"}, {2, "64x128"}, {3, "128x64"}, {4, "wave32x32"}, {5, "128x128"}, {6, "pipe64x64"},
+        {7, "pipe64x128"}, {8, "pipe128x64"}, {9, "pipe128x128"}, {10, "pipe2s64x64"}, {11, "pipe2s64x128"},
+        {12, "pipe2s128x64"}, {0, "f64_static"}, {20, "f64pipe64x64"}, {21, "f64pipe2s64x64"},
+        {22, "f64pipe2s128x64"}, {23, "f64pipe2s64x128"}};
+    std::map<int, int> cnt;
+    for (auto& kv : tune_map()) cnt[kv.second]++;
+    std::string b = "{\"classes\": " + std::to_string(tune_map().size()) +
+                    ", \"timed_here\": " + std::to_string(tuned_count());
+    for (auto& nm : names) b += std::string(", \"") + nm.second + "\": " + std::to_string(cnt[nm.first]);
+    b += "}";
     return b;
   }
   void* prepare_cfg(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc,
@@ -2456,7 +2725,8 @@ class HipExec : public Executor {
                            P->d_items + t0, P->part ? P->part : part_, nt);
       }
     } else {
-      KernelFn k = P->pipe     ? pick_pipe(P->dc, P->bm, P->bn)
+      KernelFn k = P->pipe     ? (P->mode == DT_F64 ? pick_pipe_f64(P->bm, P->bn, P->stages)
+                                                    : pick_pipe(P->dc, P->bm, P->bn, P->stages))
                    : P->padded ? pick_padded(P->dc, P->bm, P->bn, P->da == DT_FP8, P->db == DT_FP8)
                                : pick(P->mode, P->da, P->db, P->dc, P->kt);
       for (long long t0 = 0; t0 < P->nitems; t0 += maxg) {
@@ -2812,7 +3082,7 @@ class HipExec : public Executor {
     char key[128];
     int cfg = 0;
     while (std::fscanf(fp, "%127s %d", key, &cfg) == 2)
-      if (cfg >= 1 && cfg <= 9) tune_map()[key] = cfg;
+      if (cfg >= 0 && cfg <= 23) tune_map()[key] = cfg;
     std::fclose(fp);
   }
   static void save_tune_file(const std::string& key, int cfg) {

@@ -69,10 +69,31 @@ def test_heff_diag_matches_oracle_dense():
     assert np.abs(diag - np.diag(hd)).max() < 1e-10 * np.abs(np.diag(hd)).max()
 
 
+F64_KERNELS = ["static", "f64pipe64x64", "f64pipe2s64x64", "f64pipe2s128x64", "f64pipe2s64x128"]
+
+
+@pytest.mark.parametrize("kernel", F64_KERNELS)
+@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[7]], ids=["n7S1", "n8S0", "n11S1D500"])
+def test_hpsi_fp64_kernels_match_oracle(case, kernel, monkeypatch):
+    # Every FP64 kernel the tuner chooses from, forced for all H*psi launches.
+    if kernel == "static":
+        monkeypatch.setenv("DMRG_PIPE", "0")
+    else:
+        monkeypatch.setenv("DMRG_TILE", kernel)
+    print(f"[hpsi fp64 kernel] {kernel} case={case}", flush=True)
+    h, g, mps, psi, lay, dm = _setup(*case)
+    y, _ = dm.hpsi(psi)
+    ref = heff.hpsi(h, g, mps, lay, psi)
+    assert np.abs(y - ref).max() < 1e-10 * np.abs(ref).max()
+    y2, _ = dm.hpsi(psi)
+    assert np.array_equal(y, y2)
+
+
 @pytest.mark.parametrize("prec,bound,kt", [(1, 2.0 ** -24 * 64, ""), (2, 2.0 ** -8 * 8, "32"),
                                            (2, 2.0 ** -8 * 8, "64"), (2, 2.0 ** -8 * 8, "")])
 @pytest.mark.parametrize("kernel", ["lean", "generic", "64x64", "64x128", "128x64", "128x128", "pipe64x64",
-                                    "pipe64x128", "pipe128x64", "pipe128x128", "wave"])
+                                    "pipe64x128", "pipe128x64", "pipe128x128", "pipe2s64x64", "pipe2s64x128",
+                                    "pipe2s128x64", "wave"])
 def test_hpsi_low_precision_error_bound(prec, bound, kt, kernel, monkeypatch):
     # BF16 H*psi launches run on the lean padded-operand kernel unless it is
     # switched off; the generic kernel then runs with K slabs of 32 or 64.

@@ -101,7 +101,7 @@ def test_gemm_bf16_lean_and_generic_kernels_agree(m, n, k, monkeypatch):
 
 
 @pytest.mark.parametrize("tile", ["64x64", "64x128", "128x64", "128x128", "pipe64x64", "pipe64x128", "pipe128x64",
-                                  "pipe128x128"])
+                                  "pipe128x128", "pipe2s64x64", "pipe2s64x128", "pipe2s128x64"])
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (65, 63, 17), (130, 70, 300), (7, 200, 129), (200, 9, 5), (129, 257, 40)])
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
 def test_gemm_bf16_lean_tile_shapes(tile, m, n, k, ta, tb, monkeypatch):
@@ -119,6 +119,25 @@ def test_gemm_bf16_lean_tile_shapes(tile, m, n, k, ta, tb, monkeypatch):
     bound = (2 * 2.0 ** -8 + k * 2.0 ** -24) * 0.5 * (np.abs(a) @ np.abs(b)) + 2.0 ** -24 * np.abs(ref)
     assert np.all(np.isfinite(got))
     assert np.all(np.abs(got - ref) <= 4 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("tile", ["f64pipe64x64", "f64pipe2s64x64", "f64pipe2s128x64", "f64pipe2s64x128"])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (65, 63, 17), (130, 70, 300), (7, 200, 129), (200, 9, 5), (129, 257, 40)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_f64_pipelined_tile_shapes(tile, m, n, k, ta, tb, monkeypatch):
+    # The FP64 LDS-pipelined kernel on NaN-padded operands: both storage
+    # orientations of each operand, ragged edges, k tails, accumulation.
+    monkeypatch.setenv("DMRG_TILE", tile)
+    from paper_2503_20700_amd.binding import gemm_selftest
+    rng = np.random.default_rng(m + 5 * n + 11 * k)
+    a = rng.normal(size=(m, k))
+    b = rng.normal(size=(k, n))
+    c0 = rng.normal(size=(m, n))
+    got = gemm_selftest(a.T.copy() if ta else a, b.T.copy() if tb else b, C=c0, trans_a=bool(ta), trans_b=bool(tb),
+                        alpha=0.5, beta=1.0, prec=0, pad_a=True, pad_b=True)
+    ref = c0 + 0.5 * (a @ b)
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref).max() <= 1e-13 * (1.0 + np.abs(ref).max()) * k
 
 
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (5, 3, 40), (32, 32, 32), (33, 31, 65), (65, 63, 17), (7, 200, 129),

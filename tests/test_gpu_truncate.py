@@ -171,13 +171,15 @@ def test_dbss_selection_matches_oracle(direction):
             assert err <= eps
 
 
+@pytest.mark.parametrize("direction", [1, -1], ids=["right", "left"])
 @pytest.mark.parametrize("d_max", [10 ** 6, 12], ids=["complete", "truncated"])
 @pytest.mark.parametrize("case", [(8, 8, 0, 64, 3, 0), (8, 7, 1, 20, 3, 5)], ids=["s0", "s1/2"])
-def test_next_block_guess_is_the_kept_state(case, d_max):
-    # The start vector carried from (k, k+1) to (k+1, k+2): expanded into
-    # determinants through the moved MPS it is exactly the old wavefunction
-    # when nothing is discarded, and its orthogonal projection onto the kept
-    # left states otherwise (overlap = norm^2 = 1 - trunc_err).
+def test_next_block_guess_is_the_kept_state(case, d_max, direction):
+    # The start vector carried from (k, k+1) to (k+1, k+2) (or (k-1, k)):
+    # expanded into determinants through the moved MPS it is exactly the old
+    # wavefunction when nothing is discarded, and its orthogonal projection
+    # onto the kept states of the cut side otherwise (overlap = norm^2 =
+    # 1 - trunc_err).
     from oracle.mps_fock import Embedding
     from paper_2503_20700_amd.binding import DMRG
     n, ne, ts, d, k, seed = case
@@ -188,10 +190,10 @@ def test_next_block_guess_is_the_kept_state(case, d_max):
     dm = DMRG(h, g, ne, ts, keep_blocks=True, next_guess=True)
     bs, cnt = mps.bond_table()
     dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
-    err, kept = dm.truncate(psi, d_max, 0.0, 1)
-    assert dm.k == k + 1
+    err, kept = dm.truncate(psi, d_max, 0.0, direction)
+    assert dm.k == k + direction
     guess = dm.next_guess()
-    m2 = _moved_mps(mps, dm, k, 1)
+    m2 = _moved_mps(mps, dm, k, direction)
     lay2 = psi_layout(m2.left_bonds[m2.k], m2.right_bonds[m2.k + 2], ne, ts)
     old = Embedding(mps, lay).expand(psi)
     new = Embedding(m2, lay2).expand(guess)
