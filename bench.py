@@ -237,6 +237,9 @@ def main():
                          "bond kept; CAS(32,32) D=1024 fits one GPU)")
     ap.add_argument("--bulk", default="bf16", choices=["fp64", "fp32", "bf16"],
                     help="--full-sweeps: Davidson bulk matvec precision (fp32 / bf16 end with FP64 refinement)")
+    ap.add_argument("--shadow", default="", choices=["", "fp32", "bf16"],
+                    help="--full-sweeps: also solve every block with this bulk precision (+ FP64 refinement) from "
+                         "the same start vector and report the energy differences")
     ap.add_argument("--sweep", action="store_true",
                     help="time a half-sweep from the centre to the right end (operator blocks of every bond "
                          "kept; fits one GPU for CAS(32,32) D=1024, not for CAS(82,82) D=4096)")
@@ -534,20 +537,35 @@ def full_sweeps_main(args):
     start = psi
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    shadow = {"fp32": FP32, "bf16": BF16}.get(args.shadow) if args.shadow else None
     for i, (label, direction) in enumerate(plan):
         k = dm.k
         t1 = time.perf_counter()
         r = dm.davidson(start)
         t2 = time.perf_counter()
+        st = {"sweep": label, "block": [k, k + 1], "direction": direction, "davidson_s": t2 - t1,
+              "energy_Eh": r["energy"], "residual": r["resid"], "converged": r["converged"],
+              "matvecs": {"lowprec": r["n_lo"], "fp64": r["n_fp64"]}}
+        if shadow is not None:
+            # the other path's solve of the same block from the same start vector
+            dm.update_opts(hpsi_prec=shadow)
+            t4 = time.perf_counter()
+            rs = dm.davidson(start)
+            t5 = time.perf_counter()
+            dm.update_opts(hpsi_prec=prec)
+            st["shadow"] = {"davidson_s": t5 - t4, "energy_Eh": rs["energy"], "residual": rs["resid"],
+                            "converged": rs["converged"], "matvecs": {"lowprec": rs["n_lo"], "fp64": rs["n_fp64"]},
+                            "abs_dE_Eh": abs(rs["energy"] - r["energy"])}
+        t2b = time.perf_counter()
         err, kept = dm.truncate(r["psi"], w["D"], 0.0, direction)
         t3 = time.perf_counter()
-        steps.append({"sweep": label, "block": [k, k + 1], "direction": direction, "davidson_s": t2 - t1,
-                      "truncate_and_grow_s": t3 - t2, "energy_Eh": r["energy"], "residual": r["resid"],
-                      "converged": r["converged"], "matvecs": {"lowprec": r["n_lo"], "fp64": r["n_fp64"]},
-                      "trunc_err": err, "d_kept": kept})
+        st.update({"truncate_and_grow_s": t3 - t2b, "trunc_err": err, "d_kept": kept})
+        steps.append(st)
         ends[label] = r["energy"]
-        log(f"{label} block ({k},{k + 1}) dir {direction:+d}: {t3 - t1:.1f}s, E {r['energy']:.10f}, "
-            f"residual {r['resid']:.1e}, matvecs {r['n_lo']}+{r['n_fp64']}")
+        log(f"{label} block ({k},{k + 1}) dir {direction:+d}: {t2 - t1 + t3 - t2b:.1f}s, E {r['energy']:.10f}, "
+            f"residual {r['resid']:.1e}, matvecs {r['n_lo']}+{r['n_fp64']}"
+            + (f"; {args.shadow}: {st['shadow']['davidson_s']:.1f}s, dE {st['shadow']['abs_dE_Eh']:.1e}"
+               if shadow is not None else ""))
         if i + 1 < len(plan):
             start = dm.next_guess()  # carried across the cut the truncation just moved over
     torch.cuda.synchronize()
@@ -570,6 +588,22 @@ def full_sweeps_main(args):
         "setup_s": {"operator_blocks": t_env},
         "sweep_steps": steps,
     }
+    if shadow is not None:
+        sh = [st["shadow"] for st in steps]
+        trunc = sum(st["truncate_and_grow_s"] for st in steps)
+        out["value"] = sum(st["davidson_s"] for st in steps) + trunc  # the primary path alone
+        out["shadow"] = {
+            "precision": args.shadow + " bulk + FP64 refinement",
+            "what": "every block also solved with the shadow precision from the same start vector; the sweep "
+                    "continues with the primary result",
+            "seconds_same_trajectory": sum(x["davidson_s"] for x in sh) + trunc,
+            "max_abs_dE_Eh": max(x["abs_dE_Eh"] for x in sh),
+            "blocks_within_1e-6_Eh": sum(x["abs_dE_Eh"] <= 1e-6 for x in sh),
+            "blocks": len(sh),
+            "all_converged": all(x["converged"] for x in sh),
+            "matvecs": {"lowprec": sum(x["matvecs"]["lowprec"] for x in sh),
+                        "fp64": sum(x["matvecs"]["fp64"] for x in sh)},
+        }
     print(json.dumps(out), flush=True)
     dm.close()
 
