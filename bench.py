@@ -60,7 +60,25 @@ def batch_instances(count=48, master_seed=2):
     return out
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_bf16_padded_cas82_d4096.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bf16_grouped_gemm_cas82_d4096.json")
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_bf16_grouped_gemm_cas82_d4096.json")
+
+
+def measured_mfma(config):
+    """MFMA busy fraction and executed / algorithmic MFMA flops of the BF16
+    H*psi kernels, from the committed rocprofv3 counter summary of the
+    CAS(82,82) workload, or None if there is none or the kernel source
+    changed since."""
+    if config != "cas82_d4096" or not os.path.exists(MFMA_FILE):
+        return None
+    from rocprof_summary import source_sha256
+    with open(MFMA_FILE) as f:
+        m = json.load(f)
+    if m.get("source_sha256") != source_sha256():
+        return None
+    return {"busy_fraction": m["mfma_busy_fraction"], "executed_flops": m["mfma_flops_executed"],
+            "executed_over_algorithmic": m["executed_over_algorithmic"], "launches": m["launches"],
+            "source": os.path.relpath(MFMA_FILE, ROOT)}
 
 
 def measured_traffic(config):
@@ -406,6 +424,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": lo_kernel_tflops, "peak": PEAK["bf16"], "unit": "TFLOP/s",
                      "frac": lo_kernel_tflops / PEAK["bf16"], "traffic": traffic},
         "traffic_detail": traffic_detail,
+        "mfma_counters": measured_mfma(args.config),
         "cpu_baseline": base,
         "hpsi_flops": flops,
         "hpsi_flops_executed": st["hpsi_flops_executed"],

@@ -43,7 +43,8 @@ BF16_GEMMS = ("gemm_bf16_padded", "gemm_bf16_wave", "gemm_bf16_pipe")
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"(gemm_kernel|gemm_bf16_padded|gemm_bf16_pipe|gemm_bf16_wave|gemm_f64_wave|reduce_kernel|convert_kernel|"
+    m = re.search(r"(gemm_kernel|gemm_bf16_padded|gemm_bf16_pipe|gemm_bf16_wave|gemm_f64_pipe|gemm_f64_wave|reduce_kernel|"
+                  r"convert_kernel|"
                   r"pack_kernel)"
                   r"<([^>]*)>", name)
     if m:
