@@ -716,6 +716,10 @@ def batch_main(args):
         single = [dm.davidson(p) for dm, p in zip(dms, starts)]
         t_single = time.perf_counter() - t0
         batch = HpsiBatch(dms, BF16)
+        # untimed first call: builds (and tunes) the merged FP64 launches of the
+        # refinement, which the one-by-one contexts already hold from their
+        # earlier H*psi calls
+        batch.davidson(starts)
         t0 = time.perf_counter()
         got = batch.davidson(starts)
         t_batch = time.perf_counter() - t0
@@ -727,8 +731,9 @@ def batch_main(args):
                "matvecs_batched": {"bf16": sum(r["n_lo"] for r in got), "fp64": sum(r["n_fp64"] for r in got)},
                "matvecs_one_by_one": {"bf16": sum(r["n_lo"] for r in single),
                                       "fp64": sum(r["n_fp64"] for r in single)},
-               "solver": f"BF16 Davidson, then Jacobi-Davidson FP64 refinement ({args.jd_inner} BF16 CG steps per "
-                         "correction) to residual 1e-7, from the random start vector"}
+               "solver": "BF16 Davidson, then FP64 refinement to residual 1e-7 from the random start vector ("
+                         + (f"Jacobi-Davidson, {args.jd_inner} BF16 CG steps per correction)" if args.jd_inner
+                            else "Davidson with FP64 matvecs from the BF16 phase's lowest Ritz vectors)")}
         log(f"Davidson of 48 instances: batched {t_batch:.1f}s, one by one {t_single:.1f}s, "
             f"max |dE| {dav['max_abs_dE_batched_vs_one_by_one_Eh']:.1e}")
     b16 = res["bf16"]
