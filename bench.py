@@ -161,7 +161,7 @@ def accuracy_case(DMRG, BF16, FP64, jd_inner):
             "converged": bool(out["bf16+fp64"]["converged"] and out["fp64"]["converged"])}
 
 
-def converged_step(dm, psi, D, jd_inner, BF16, FP64, compare_from_random=False):
+def converged_step(dm, psi, D, jd_inner, BF16, FP64, compare_from_random=False, mid_fp32=True, FP32=1):
     """One two-site DMRG step at the workload's block, solved to the paper's
     Davidson residual 1e-7 (Sec. "Numerical procedure"), then truncated to D
     multiplets with the left operator block grown across the new bond.
@@ -188,8 +188,13 @@ def converged_step(dm, psi, D, jd_inner, BF16, FP64, compare_from_random=False):
     log(f"BF16 phase from the random start: {t_pre:.1f}s, {r0['n_lo']} matvecs, residual {r0['resid']:.2e}")
     x0 = r0["psi"]
     runs = {}
-    dm.update_opts(hpsi_prec=BF16, davidson_max_iter=400, davidson_lowprec_iter=0, davidson_refine_iter=400,
-                   davidson_jd_inner=jd_inner)
+    if mid_fp32:
+        # FP32 matvecs from the end of the BF16 phase down to the FP32 floor, then FP64
+        dm.update_opts(hpsi_prec=FP32, davidson_max_iter=400, davidson_lowprec_iter=400, davidson_refine_iter=400,
+                       davidson_jd_inner=0)
+    else:
+        dm.update_opts(hpsi_prec=BF16, davidson_max_iter=400, davidson_lowprec_iter=0, davidson_refine_iter=400,
+                       davidson_jd_inner=jd_inner)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs["mixed"] = dm.davidson(x0)
@@ -201,10 +206,13 @@ def converged_step(dm, psi, D, jd_inner, BF16, FP64, compare_from_random=False):
     runs["fp64"] = dm.davidson(psi if compare_from_random else x0)
     t_64 = time.perf_counter() - t0
     rm, r6 = runs["mixed"], runs["fp64"]
+    mv = ({"bf16": r0["n_lo"], "fp32": rm["n_lo"], "fp64": r0["n_fp64"] + rm["n_fp64"]} if mid_fp32 else
+          {"bf16": r0["n_lo"] + rm["n_lo"], "fp64": r0["n_fp64"] + rm["n_fp64"]})
     out["mixed"] = {"seconds": t_pre + t_ref, "refinement_seconds": t_ref, "energy_Eh": rm["energy"],
-                    "residual": rm["resid"], "converged": rm["converged"],
-                    "matvecs": {"bf16": r0["n_lo"] + rm["n_lo"], "fp64": r0["n_fp64"] + rm["n_fp64"]},
-                    "refinement": (f"Jacobi-Davidson, {jd_inner} BF16 CG steps per correction" if jd_inner
+                    "residual": rm["resid"], "converged": rm["converged"], "matvecs": mv,
+                    "refinement": ("Davidson with FP32 matvecs from the end of the BF16 phase down to 1e-6 of the "
+                                   "spectrum scale, then FP64 matvecs from its lowest Ritz vectors" if mid_fp32
+                                   else f"Jacobi-Davidson, {jd_inner} BF16 CG steps per correction" if jd_inner
                                    else "Davidson with FP64 matvecs from the BF16 phase's 4 lowest Ritz vectors")}
     out["fp64"] = {"seconds": t_64, "energy_Eh": r6["energy"], "residual": r6["resid"], "converged": r6["converged"],
                    "matvecs": {"fp64": r6["n_fp64"]},
@@ -240,6 +248,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dmrg-step", action="store_true", help="skip the timed Davidson + truncation step")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8-operand H*psi timing")
+    ap.add_argument("--no-mid-fp32", action="store_true",
+                    help="converged step / sweep: refine from the BF16 phase with FP64 matvecs only (no FP32 phase)")
     ap.add_argument("--compare-from-random", action="store_true",
                     help="converged step: run the FP64 solve from the random start too (solver-level speedup)")
     ap.add_argument("--accuracy-small", action="store_true",
@@ -280,7 +290,7 @@ def main():
         return
 
     import torch
-    from paper_2503_20700_amd.binding import BF16, DMRG, FP8, FP64
+    from paper_2503_20700_amd.binding import BF16, DMRG, FP8, FP32, FP64
     from synth.mps import random_mps, random_psi
 
     dev = torch.device("cuda:0")
@@ -384,7 +394,8 @@ def main():
     step = None
     if not args.no_dmrg_step:
         log("converged DMRG step: mixed precision and FP64 from the same start vector")
-        step = converged_step(dm, psi, w["D"], args.jd_inner, BF16, FP64, args.compare_from_random)
+        step = converged_step(dm, psi, w["D"], args.jd_inner, BF16, FP64, args.compare_from_random,
+                              mid_fp32=not args.no_mid_fp32, FP32=FP32)
 
     acc = None
     if args.accuracy_small:
@@ -468,10 +479,10 @@ def sweep_main(args):
     psi, _ = random_psi(mps, seed=w["seed"] + 1)
     total_blocks = w["n"] - 1 - w["k"]  # blocks (k, k+1) .. (n-2, n-1)
     steps_max = args.sweep_steps if args.sweep_steps > 0 else total_blocks
-    keep = 1 if steps_max >= total_blocks else max(2, steps_max)
+    keep = 1 if steps_max >= total_blocks else -max(2, steps_max)  # right blocks only: the sweep moves right
     dm = DMRG(w["h"], w["g"], w["N"], w["two_s"], hpsi_prec=BF16, davidson_max_iter=400,
               davidson_max_subspace=48, work_budget_elems=args.x_budget, davidson_jd_inner=args.jd_inner,
-              keep_blocks=keep, next_guess=True)
+              keep_blocks=keep, next_guess=True, davidson_mid_fp32=not args.no_mid_fp32)
     bs, cnt = mps.bond_table()
     t0 = time.perf_counter()
     dm.set_mps(w["k"], bs, cnt, mps.site_blocks_flat())

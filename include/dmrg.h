@@ -83,7 +83,9 @@ typedef struct {
                                   dmrg_set_mps builds, so dmrg_truncate can move
                                   the two-site block (memory grows with n);
                                   m >= 2: keep only the m bonds nearest the block
-                                  on each side (m moves); 0: none                 */
+                                  on each side (m moves); -m <= -2: only the m
+                                  nearest on the right side (m moves to the
+                                  right, nothing kept for a move back); 0: none */
   int davidson_refine_iter;    /* iterations of the FP64 refinement phase when
                                   hpsi_prec is not FP64; 0: davidson_max_iter     */
   int davidson_jd_inner;       /* refinement with hpsi_prec not FP64: 0 expands the
@@ -108,6 +110,12 @@ typedef struct {
                                   fails with DMRG_ERR_BUDGET instead of exceeding it
                                   (the executor's task lists and split-K partial
                                   tiles come on top); 0: no cap                     */
+  int davidson_mid_fp32;       /* 1 (hpsi_prec BF16 or FP8): between the low-
+                                  precision phase and the FP64 refinement, a phase
+                                  with FP32 matvecs from the low-precision phase's
+                                  lowest Ritz vectors, until the residual is 1e-6
+                                  of the spectrum scale or stalls; its matvecs
+                                  count as low-precision ones                      */
 } dmrg_opts;
 
 /* Create a context; copies h (n*n) and g (n^4).  h must be symmetric and g

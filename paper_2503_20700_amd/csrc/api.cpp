@@ -51,7 +51,9 @@ extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, 
   if (o->hpsi_graph < 0 || o->hpsi_graph > 1) return fail(DMRG_ERR_ARG, "dmrg_create: hpsi_graph must be 0 or 1");
   if (o->next_guess < 0 || o->next_guess > 1) return fail(DMRG_ERR_ARG, "dmrg_create: next_guess must be 0 or 1");
   if (o->hbm_budget_bytes < 0) return fail(DMRG_ERR_ARG, "dmrg_create: negative hbm_budget_bytes");
-  if (o->keep_blocks < 0) return fail(DMRG_ERR_ARG, "dmrg_create: negative keep_blocks");
+  if (o->keep_blocks == -1) return fail(DMRG_ERR_ARG, "dmrg_create: keep_blocks -1 (right side only needs -m <= -2)");
+  if (o->davidson_mid_fp32 < 0 || o->davidson_mid_fp32 > 1)
+    return fail(DMRG_ERR_ARG, "dmrg_create: davidson_mid_fp32 must be 0 or 1");
   const size_t n2 = (size_t)n * n, n4 = n2 * n2;
   if (!finite_all(h, n2) || !finite_all(g, n4)) return fail(DMRG_ERR_NONFINITE, "dmrg_create: non-finite integral");
   {
@@ -107,8 +109,9 @@ extern "C" int dmrg_update_opts(dmrg_ctx* c, const dmrg_opts* o) {
   if (o->davidson_max_iter < 0 || o->davidson_refine_iter < 0 || o->davidson_max_subspace < 0 ||
       o->davidson_jd_inner < 0 || o->davidson_lowprec_iter < -1 || !(o->davidson_tol >= 0.0))
     return fail(DMRG_ERR_ARG, "dmrg_update_opts: negative Davidson budget or tolerance");
-  if (o->hpsi_graph < 0 || o->hpsi_graph > 1 || o->next_guess < 0 || o->next_guess > 1)
-    return fail(DMRG_ERR_ARG, "dmrg_update_opts: hpsi_graph and next_guess must be 0 or 1");
+  if (o->hpsi_graph < 0 || o->hpsi_graph > 1 || o->next_guess < 0 || o->next_guess > 1 || o->davidson_mid_fp32 < 0 ||
+      o->davidson_mid_fp32 > 1)
+    return fail(DMRG_ERR_ARG, "dmrg_update_opts: hpsi_graph, next_guess and davidson_mid_fp32 must be 0 or 1");
   c->opts = *o;
   return DMRG_OK;
 }
@@ -195,10 +198,11 @@ extern "C" int dmrg_set_mps(dmrg_ctx* c, int k, const int* bs, const int* counts
                    c->ex->host_profile().c_str());
       std::fflush(stderr);
     };
-    // keep_blocks 1: every bond; m >= 2: the m bonds nearest the block on each side
+    // keep_blocks 1: every bond; m >= 2: the m bonds nearest the block on each
+    // side; -m <= -2: the m nearest on the right side only
     const int kb = c->opts.keep_blocks;
     auto keep_left = [&](int bond) { return kb == 1 || (kb >= 2 && bond >= k - kb); };
-    auto keep_right = [&](int bond) { return kb == 1 || (kb >= 2 && bond <= k + 2 + kb); };
+    auto keep_right = [&](int bond) { return kb == 1 || (kb >= 2 && bond <= k + 2 + kb) || (kb <= -2 && bond <= k + 2 - kb); };
     for (auto& h : C.Lhist)
       if (h) C.free_block(*h);
     for (auto& h : C.Rhist)

@@ -261,6 +261,8 @@ extern "C" int dmrg_batch_davidson(dmrg_batch* b, double* const* psi, double* en
     // the merged launches every phase can ask for, built before the threads start
     for (dmrg_ctx* x : b->ctx) {
       merged_for(b, x->opts.hpsi_prec);
+      if (x->opts.davidson_mid_fp32 && (x->opts.hpsi_prec == DMRG_BF16 || x->opts.hpsi_prec == DMRG_FP8))
+        merged_for(b, DMRG_FP32);
       merged_for(b, DMRG_FP64);
     }
   } catch (const std::bad_alloc& e) {

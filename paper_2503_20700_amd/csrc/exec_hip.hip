@@ -2565,7 +2565,15 @@ class HipExec : public Executor {
       else choose_tile(jobs, terms, P->bm, P->bn);
     } else if (P->mode == DT_F64 && dc == DT_F64 && !std::getenv("DMRG_NO_F64_WAVE")) {
       P->wave = choose_wave(jobs, terms, 16);
-      if (P->wave) P->bm = P->bn = 32;
+      if (P->wave) {
+        P->bm = P->bn = 32;
+      } else if (P->pad64 && !(std::getenv("DMRG_PIPE") && std::atoi(std::getenv("DMRG_PIPE")) == 0)) {
+        // the two-stage 64 x 64 pipelined tile: what the tuner chose for every
+        // FP64 H*psi launch class of the CAS(32,32) and CAS(82,82) workloads
+        P->pipe = true;
+        P->bm = P->bn = 64;
+        P->stages = 2;
+      }
     }
     try {
       if (!f8) pick(P->mode, da, db, dc, P->kt);  // validate
@@ -2603,9 +2611,12 @@ class HipExec : public Executor {
                       (dc == DT_BF16 || dc == DT_F32);
     const bool f64 = da == DT_F64 && db == DT_F64 && dc == DT_F64;
     const bool no_pipe = std::getenv("DMRG_PIPE") && std::atoi(std::getenv("DMRG_PIPE")) == 0;
+    // FP64 launches take the static rule (which picks the pipelined tile the
+    // tuner chose for every FP64 class measured) unless DMRG_TUNE_F64 is set:
+    // timing five FP64 candidates costs seconds per block of a sweep
     if ((!lowp && !f64) || jobs.empty() || (std::getenv("DMRG_TUNE") && std::atoi(std::getenv("DMRG_TUNE")) == 0) ||
         std::getenv("DMRG_TILE") || std::getenv("DMRG_WAVE") || std::getenv("DMRG_NO_PADDED_KERNEL") ||
-        (f64 && (no_pipe || std::getenv("DMRG_NO_F64_WAVE"))))
+        (f64 && (no_pipe || std::getenv("DMRG_NO_F64_WAVE") || !std::getenv("DMRG_TUNE_F64"))))
       return prepare(jobs, terms, da, db, dc);
     // candidates: BF16 / FP8 padded launches 1..12 (FP8 1..3); FP64 launches
     // the static rule (gemm_kernel or gemm_f64_wave) and the pipelined tiles

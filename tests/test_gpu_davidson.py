@@ -106,3 +106,29 @@ def test_fp8_davidson_with_fp64_refinement_reaches_the_fp64_energy():
     assert r["converged"] and r["resid"] <= 1e-7
     assert r["n_lo"] > 0 and r["n_fp64"] > 0
     assert abs(r["energy"] - e_ref) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [2, 3], ids=["bf16", "fp8"])
+@pytest.mark.parametrize("case", [(8, 8, 0, 64, 3, 0), (7, 7, 1, 16, 2, 3)], ids=["cas88_s0", "cas77_s1/2"])
+def test_davidson_fp32_middle_phase(prec, case):
+    """Low-precision phase, then FP32 matvecs from its Ritz vectors, then FP64
+    refinement (davidson_mid_fp32): the residual 1e-7, the dense eigenvalue
+    to 1e-6 Eh, and no more FP64 matvecs than without the FP32 phase."""
+    from paper_2503_20700_amd.binding import DMRG
+    n, ne, ts, d, k, seed = case
+    print(f"[davidson mid fp32] prec={prec} case={case}", flush=True)
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    e_ref = np.linalg.eigvalsh(heff.HeffDefinition(h, g, mps, lay).dense())[0]
+    res = {}
+    for mid in (False, True):
+        dm = DMRG(h, g, ne, ts, hpsi_prec=prec, davidson_max_iter=300, davidson_mid_fp32=mid)
+        bs, cnt = mps.bond_table()
+        dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+        r = dm.davidson(psi)
+        dm.close()
+        assert r["converged"] and r["resid"] <= 1e-7, (mid, r["resid"])
+        assert abs(r["energy"] - e_ref) <= 1e-6
+        res[mid] = r
+    assert res[True]["n_fp64"] <= res[False]["n_fp64"]

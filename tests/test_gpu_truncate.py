@@ -204,3 +204,25 @@ def test_next_block_guess_is_the_kept_state(case, d_max, direction):
         assert np.abs(new - old).max() < 1e-12
     else:
         assert err > 1e-6
+
+
+def test_keep_blocks_right_side_only():
+    # keep_blocks -m keeps the m nearest right blocks only: m moves to the
+    # right, none to the left (keep_blocks m keeps both sides)
+    from paper_2503_20700_amd.binding import DMRG
+    n, ne, ts, d, k, seed = 8, 8, 0, 64, 3, 0
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 10)
+    psi, lay = random_psi(mps, seed=seed + 20)
+    bs, cnt = mps.bond_table()
+    for keep, moves in ((-2, [(1, 4), (1, 5), (1, -1)]), (-2, [(-1, -1)]), (2, [(-1, 2)])):
+        dm = DMRG(h, g, ne, ts, keep_blocks=keep)
+        dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+        for direction, want in moves:
+            _, nel = dm.psi_layout()
+            p = np.random.default_rng(3).normal(size=nel)
+            dm.truncate(p, 10 ** 6, 0.0, direction)
+            assert dm.k == want, (keep, direction, dm.k, want)
+            if want < 0:
+                break
+        dm.close()
