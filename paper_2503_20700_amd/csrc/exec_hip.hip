@@ -2240,8 +2240,9 @@ ReduceFn pick_reduce(int mode, int dc) {
 // launch has at least ~min_items items (16k work-groups fill 256 CUs several
 // times over; the wave kernels take four items per work-group and ask for
 // 64k) but never below min_steps (64: a floor of 16 for the wave kernels
-// added reduction work and gained nothing).  Items are issued heaviest first (longest
-// processing time first), which bounds the tail of the launch.
+// added reduction work and gained nothing; 400 for the pipelined kernels).
+// Items are issued heaviest first (longest processing time first), which
+// bounds the tail of the launch, then grouped by shared A slab per XCD.
 void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int kt, int bm, int bn,
                 double min_items, double min_steps, std::vector<WorkItem>& items, std::vector<RedItem>& reds,
                 long long& nslots) {
@@ -2320,25 +2321,40 @@ void plan_items(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& ter
     const char* e = std::getenv("DMRG_XCD_GROUP");
     if (!(e && std::atoi(e) == 0) && items.size() > 64) {
       constexpr int kXcd = 8;
-      std::vector<std::vector<WorkItem>> q(kXcd);
-      std::vector<double> load(kXcd, 0.0);
-      std::map<std::tuple<int, int, int>, std::vector<size_t>> groups;
-      std::vector<std::tuple<int, int, int>> order;
+      // group by (job, row tile, segment start) with a sort, not a map: a
+      // stage-L launch has about a million items
+      struct K {
+        int job, ti, tbeg;
+        size_t pos;
+      };
+      std::vector<K> keys(work.size());
       for (size_t i = 0; i < work.size(); ++i) {
         const WorkItem& w = work[i].second;
-        const auto key = std::make_tuple(w.job, w.ti, w.tbeg);
-        auto it = groups.find(key);
-        if (it == groups.end()) {
-          order.push_back(key);
-          it = groups.emplace(key, std::vector<size_t>()).first;
-        }
-        it->second.push_back(i);
+        keys[i] = K{w.job, w.ti, w.tbeg, i};
       }
-      for (const auto& key : order) {
+      std::sort(keys.begin(), keys.end(), [](const K& a, const K& b) {
+        if (a.job != b.job) return a.job < b.job;
+        if (a.ti != b.ti) return a.ti < b.ti;
+        if (a.tbeg != b.tbeg) return a.tbeg < b.tbeg;
+        return a.pos < b.pos;
+      });
+      // groups as [begin, end) ranges of keys, ordered by their first LPT position
+      std::vector<std::pair<size_t, size_t>> grp;
+      for (size_t i = 0; i < keys.size();) {
+        size_t j = i + 1;
+        while (j < keys.size() && keys[j].job == keys[i].job && keys[j].ti == keys[i].ti && keys[j].tbeg == keys[i].tbeg)
+          ++j;
+        grp.push_back({i, j});
+        i = j;
+      }
+      std::sort(grp.begin(), grp.end(), [&](const auto& a, const auto& b) { return keys[a.first].pos < keys[b.first].pos; });
+      std::vector<std::vector<WorkItem>> q(kXcd);
+      std::vector<double> load(kXcd, 0.0);
+      for (const auto& gr : grp) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        for (size_t i : groups[key]) {
-          q[x].push_back(work[i].second);
-          load[x] += work[i].first;
+        for (size_t i = gr.first; i < gr.second; ++i) {
+          q[x].push_back(work[keys[i].pos].second);
+          load[x] += work[keys[i].pos].first;
         }
       }
       size_t pos = 0;
@@ -2617,7 +2633,13 @@ class HipExec : public Executor {
     try {
       if (!f8) pick(P->mode, da, db, dc, P->kt);  // validate
       if (terms.size() > (size_t)0x7fffffff) throw std::runtime_error("executor: too many products in one launch");
-      plan_items(jobs, terms, P->kt, P->bm, P->bn, P->wave ? 65536.0 : 16384.0, 64.0, items, reds, P->nslots);
+      // the pipelined kernels keep several slabs in flight per work-group and
+      // pay for the partial tiles of split items: longer product segments
+      // (at least 400 slabs) measured best for them at CAS(82,82) (BF16
+      // H*psi 304 -> 294 ms against the 64-slab floor; 160 slabs 306 ms,
+      // 800 slabs 300 ms, 1600 slabs 308 ms)
+      plan_items(jobs, terms, P->kt, P->bm, P->bn, P->wave ? 65536.0 : 16384.0, P->pipe ? 400.0 : 64.0, items, reds,
+                 P->nslots);
       P->nitems = (long long)items.size();
       P->nreds = (long long)reds.size();
       if (P->nreds) pick_reduce(P->mode, dc);
