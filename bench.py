@@ -726,6 +726,23 @@ def batch_main(args):
         t0 = time.perf_counter()
         single = [dm.davidson(p) for dm, p in zip(dms, starts)]
         t_single = time.perf_counter() - t0
+        # the same solves with each iteration's device work replayed from
+        # recorded graphs (davidson_graph): the first call records them
+        for dm in dms:
+            dm.update_opts(davidson_graph=True)
+        t0 = time.perf_counter()
+        rec1 = [dm.davidson(p) for dm, p in zip(dms, starts)]
+        t_rec1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rec2 = [dm.davidson(p) for dm, p in zip(dms, starts)]
+        t_rec2 = time.perf_counter() - t0
+        for dm in dms:
+            dm.update_opts(davidson_graph=False)
+        same = all(a["energy"] == b["energy"] == c["energy"] and np.array_equal(a["psi"], b["psi"])
+                   and np.array_equal(a["psi"], c["psi"]) and (a["n_lo"], a["n_fp64"]) == (b["n_lo"], b["n_fp64"])
+                   for a, b, c in zip(single, rec1, rec2))
+        log(f"Davidson of 48 instances one by one: eager {t_single:.2f}s, recorded iterations {t_rec2:.2f}s "
+            f"(first call, recording included, {t_rec1:.2f}s); identical results: {same}")
         batch = HpsiBatch(dms, BF16)
         # untimed first call: builds (and tunes) the merged FP64 launches of the
         # refinement, which the one-by-one contexts already hold from their
@@ -736,6 +753,8 @@ def batch_main(args):
         t_batch = time.perf_counter() - t0
         batch.close()
         dav = {"one_by_one_s": t_single, "batched_s": t_batch, "speedup": t_single / t_batch,
+               "one_by_one_recorded_iterations_s": t_rec2, "one_by_one_recorded_iterations_first_call_s": t_rec1,
+               "recorded_iterations_identical_to_eager": same,
                "all_converged": all(r["converged"] for r in got + single),
                "max_resid": max(r["resid"] for r in got),
                "max_abs_dE_batched_vs_one_by_one_Eh": max(abs(a["energy"] - b["energy"]) for a, b in zip(got, single)),

@@ -116,6 +116,15 @@ typedef struct {
                                   lowest Ritz vectors, until the residual is 1e-6
                                   of the spectrum scale or stalls; its matvecs
                                   count as low-precision ones                      */
+  int davidson_graph;          /* 1: record the device work of a Davidson
+                                  iteration (Ritz vector, residual, new basis
+                                  vector, its H*psi and projections) as two HIP
+                                  graphs per precision and basis size, replayed
+                                  with the host's Rayleigh-Ritz coefficients in
+                                  between; same results bit for bit as 0.  Not
+                                  used with davidson_jd_inner > 0 in the
+                                  refinement, in dmrg_batch_davidson, or while
+                                  dmrg_kernel_timing records                       */
 } dmrg_opts;
 
 /* Create a context; copies h (n*n) and g (n^4).  h must be symmetric and g

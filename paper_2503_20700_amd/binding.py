@@ -35,7 +35,8 @@ class Opts(ct.Structure):
                 ("work_budget_elems", ct.c_longlong), ("keep_blocks", ct.c_int),
                 ("davidson_refine_iter", ct.c_int), ("davidson_jd_inner", ct.c_int),
                 ("davidson_lowprec_iter", ct.c_int), ("hpsi_graph", ct.c_int), ("next_guess", ct.c_int),
-                ("hbm_budget_bytes", ct.c_longlong), ("davidson_mid_fp32", ct.c_int)]
+                ("hbm_budget_bytes", ct.c_longlong), ("davidson_mid_fp32", ct.c_int),
+                ("davidson_graph", ct.c_int)]
 
 
 _LIBS = {}
@@ -217,7 +218,7 @@ class DMRG:
     def __init__(self, h, g, n_elec, two_s, e_core=0.0, davidson_tol=1e-7, davidson_max_iter=60,
                  davidson_max_subspace=24, hpsi_prec=FP64, work_budget_elems=0, keep_blocks=False,
                  davidson_refine_iter=0, davidson_jd_inner=0, davidson_lowprec_iter=-1, hpsi_graph=False,
-                 next_guess=False, hbm_budget_bytes=0, davidson_mid_fp32=False, lib=None):
+                 next_guess=False, hbm_budget_bytes=0, davidson_mid_fp32=False, davidson_graph=False, lib=None):
         self.lib = load(lib)
         h = np.ascontiguousarray(h, dtype=np.float64)
         g = np.ascontiguousarray(g, dtype=np.float64)
@@ -225,7 +226,7 @@ class DMRG:
         self.opts = Opts(n, n_elec, two_s, e_core, davidson_tol, davidson_max_iter, davidson_max_subspace,
                          hpsi_prec, work_budget_elems, int(keep_blocks), davidson_refine_iter,
                          davidson_jd_inner, davidson_lowprec_iter, int(hpsi_graph), int(next_guess),
-                         int(hbm_budget_bytes), int(davidson_mid_fp32))
+                         int(hbm_budget_bytes), int(davidson_mid_fp32), int(davidson_graph))
         self._h = ct.c_void_p()
         self._batches = weakref.WeakSet()
         self._check(self.lib.dmrg_create(ct.byref(self._h), ct.byref(self.opts), _dp(h), _dp(g)))

@@ -54,6 +54,8 @@ extern "C" int dmrg_create(dmrg_ctx** out, const dmrg_opts* o, const double* h, 
   if (o->keep_blocks == -1) return fail(DMRG_ERR_ARG, "dmrg_create: keep_blocks -1 (right side only needs -m <= -2)");
   if (o->davidson_mid_fp32 < 0 || o->davidson_mid_fp32 > 1)
     return fail(DMRG_ERR_ARG, "dmrg_create: davidson_mid_fp32 must be 0 or 1");
+  if (o->davidson_graph < 0 || o->davidson_graph > 1)
+    return fail(DMRG_ERR_ARG, "dmrg_create: davidson_graph must be 0 or 1");
   const size_t n2 = (size_t)n * n, n4 = n2 * n2;
   if (!finite_all(h, n2) || !finite_all(g, n4)) return fail(DMRG_ERR_NONFINITE, "dmrg_create: non-finite integral");
   {
@@ -110,8 +112,9 @@ extern "C" int dmrg_update_opts(dmrg_ctx* c, const dmrg_opts* o) {
       o->davidson_jd_inner < 0 || o->davidson_lowprec_iter < -1 || !(o->davidson_tol >= 0.0))
     return fail(DMRG_ERR_ARG, "dmrg_update_opts: negative Davidson budget or tolerance");
   if (o->hpsi_graph < 0 || o->hpsi_graph > 1 || o->next_guess < 0 || o->next_guess > 1 || o->davidson_mid_fp32 < 0 ||
-      o->davidson_mid_fp32 > 1)
-    return fail(DMRG_ERR_ARG, "dmrg_update_opts: hpsi_graph, next_guess and davidson_mid_fp32 must be 0 or 1");
+      o->davidson_mid_fp32 > 1 || o->davidson_graph < 0 || o->davidson_graph > 1)
+    return fail(DMRG_ERR_ARG,
+                "dmrg_update_opts: hpsi_graph, next_guess, davidson_mid_fp32 and davidson_graph must be 0 or 1");
   c->opts = *o;
   return DMRG_OK;
 }

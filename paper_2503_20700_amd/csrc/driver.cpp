@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <random>
@@ -86,6 +87,7 @@ void jacobi_eig(int m, std::vector<double> A, std::vector<double>& w, std::vecto
 
 struct Workspace {
   int bV = -1, bW = -1, bx = -1, bhx = -1, br = -1, bt = -1, bp = -1, bq = -1, bs = -1;
+  int bc = -1;  // scalars of the recorded iterations (layout: enum Cf)
   int64_t n = 0;
   int mmax = 0;
 };
@@ -95,6 +97,48 @@ constexpr int kKeep = 4;  // Ritz vectors kept at a restart
 constexpr int kStall = 6;  // low-precision phase: iterations over which the residual must fall
 
 double* P(dmrg_ctx* c, int b) { return (double*)c->C->ptr(b); }
+
+// Device scalars of a recorded Davidson iteration (offsets into ws.bc):
+// Ritz coefficients y, theta, <r,r>, <t,t>, 1/||t||, the orthogonalisation
+// coefficients, and the new row and column of the projected matrix.
+enum Cf : int { CF_Y = 0, CF_THETA = 64, CF_RR = 65, CF_TT = 66, CF_INV = 67, CF_ORTH = 68, CF_ROW = 132,
+                CF_COL = 196, CF_SIZE = 260 };
+
+// Davidson iterations recorded as graphs (opts.davidson_graph): while the
+// basis holds m < mmax vectors, an iteration is the host's Rayleigh-Ritz
+// step and stop tests plus two recorded sequences, each replayed after the
+// host has written the scalars it needs:
+//   part 1: x = V y, Hx = W y, r = Hx - theta x, <r,r>, t = the
+//           preconditioned residual orthogonalised against V twice, <t,t>;
+//   part 2: V_m = t / ||t||, W_m = H V_m, <W_j, V_m> and <V_j, W_m>, j <= m.
+// They issue the launches of the eager iteration with the same scalars, so
+// the results are the same bit for bit.  Not used for Jacobi-Davidson
+// corrections (their CG steps branch on the host), by the batched solve,
+// or while kernel timing records.
+bool dav_graph_on(dmrg_ctx* c, int jd_steps) {
+  return c->opts.davidson_graph && jd_steps == 0 && !c->mv_hook && c->ex->graphs() && !c->ex->timing_on();
+}
+
+void* dav_graph(dmrg_ctx* c, int prec, int m, int part, const std::function<void()>& body) {
+  Executor* ex = c->ex.get();
+  if (c->dav_gen != ex->scratch_generation()) {
+    c->drop_dav_graphs();
+    c->dav_gen = ex->scratch_generation();
+  }
+  const int key = (prec * 64 + m) * 2 + part;
+  auto it = c->dav_graphs.find(key);
+  if (it != c->dav_graphs.end()) return it->second;
+  ex->capture_begin();
+  try {
+    body();
+  } catch (...) {
+    ex->capture_abort();
+    throw;
+  }
+  void* g = ex->capture_end();
+  c->dav_graphs[key] = g;
+  return g;
+}
 
 // Ritz vectors carried from the low-precision phase into the FP64 phase
 // (DMRG_REFINE_KEEP overrides; 1 carries only the Ritz vector).
@@ -237,6 +281,8 @@ PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int
     }
     res.ritz_kept = kq;
   };
+  const bool graph = dav_graph_on(c, jd_steps);
+  double* cf = graph ? P(c, ws.bc) : nullptr;
   for (int it = 0; it < max_iter; ++it) {
     // Rayleigh-Ritz on span(V)
     std::vector<double> Gm((size_t)m * m);
@@ -246,11 +292,37 @@ PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int
     const double theta = w[0];
     std::vector<double> y0(m);
     for (int i = 0; i < m; ++i) y0[i] = Y[(size_t)i * m + 0];
-    ex->combine(x, V, n, m, y0.data(), n, 0.0);
-    ex->combine(hx, W, n, m, y0.data(), n, 0.0);
-    ex->axpby(r, 1.0, hx, -theta, x, n);
-    double rr = 0.0;
-    ex->multidot(r, n, 1, r, n, &rr);
+    double rr = 0.0, tt = 0.0;
+    const bool rec = graph && m < mmax;  // this iteration runs the recorded parts
+    if (rec) {
+      const int mm = m;
+      void* g1 = dav_graph(c, prec, mm, 0, [&] {
+        ex->combine_dev(x, V, n, mm, cf + CF_Y, 1.0, n, 0.0);
+        ex->combine_dev(hx, W, n, mm, cf + CF_Y, 1.0, n, 0.0);
+        ex->axpby_dev(r, 1.0, nullptr, hx, -1.0, cf + CF_THETA, x, n);
+        ex->multidot_dev(r, n, 1, r, n, cf + CF_RR);
+        ex->precond_dev(t, r, diag, cf + CF_THETA, 1e-8, n);
+        for (int pass = 0; pass < 2; ++pass) {
+          ex->multidot_dev(V, n, mm, t, n, cf + CF_ORTH);
+          ex->combine_dev(t, V, n, mm, cf + CF_ORTH, -1.0, n, 1.0);
+        }
+        ex->multidot_dev(t, n, 1, t, n, cf + CF_TT);
+      });
+      std::vector<double> up(CF_THETA + 1, 0.0);
+      for (int i = 0; i < m; ++i) up[CF_Y + i] = y0[i];
+      up[CF_THETA] = theta;
+      ex->upload(cf, up.data(), up.size() * 8);
+      ex->replay(g1);
+      double st[2];
+      ex->download(st, cf + CF_RR, sizeof st);
+      rr = st[0];
+      tt = st[1];
+    } else {
+      ex->combine(x, V, n, m, y0.data(), n, 0.0);
+      ex->combine(hx, W, n, m, y0.data(), n, 0.0);
+      ex->axpby(r, 1.0, hx, -theta, x, n);
+      ex->multidot(r, n, 1, r, n, &rr);
+    }
     res.theta = theta;
     res.resid = std::sqrt(std::max(rr, 0.0));
     if (std::getenv("DMRG_VERBOSE"))
@@ -293,21 +365,24 @@ PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int
     }
     // new direction: Jacobi-Davidson correction (low-precision inner solve)
     // or the diagonally preconditioned residual t = (theta - D)^-1 r;
-    // orthogonalised against V twice
-    bool have_t = false;
-    if (jd_steps > 0) {
-      res.inner_matvecs += jd_correction(c, ws, jd_prec, theta, jd_steps);
-      have_t = dot(ex, t, t, n) > 0.0;
+    // orthogonalised against V twice (done by the recorded part 1 already)
+    if (!rec) {
+      bool have_t = false;
+      if (jd_steps > 0) {
+        res.inner_matvecs += jd_correction(c, ws, jd_prec, theta, jd_steps);
+        have_t = dot(ex, t, t, n) > 0.0;
+      }
+      if (!have_t) ex->precond(t, r, diag, theta, 1e-8, n);
+      for (int pass = 0; pass < 2; ++pass) {
+        ex->multidot(V, n, m, t, n, tmp.data());
+        for (int i = 0; i < m; ++i) tmp[i] = -tmp[i];
+        ex->combine(t, V, n, m, tmp.data(), n, 1.0);
+      }
+      ex->multidot(t, n, 1, t, n, &tt);
     }
-    if (!have_t) ex->precond(t, r, diag, theta, 1e-8, n);
-    for (int pass = 0; pass < 2; ++pass) {
-      ex->multidot(V, n, m, t, n, tmp.data());
-      for (int i = 0; i < m; ++i) tmp[i] = -tmp[i];
-      ex->combine(t, V, n, m, tmp.data(), n, 1.0);
-    }
-    double tt = 0.0;
-    ex->multidot(t, n, 1, t, n, &tt);
+    bool fell_back = false;
     if (!(tt > 1e-28)) {
+      fell_back = true;
       // preconditioned residual lies in the basis: fall back to the residual
       ex->copy_d2d(t, r, (size_t)n * 8);
       for (int pass = 0; pass < 2; ++pass) {
@@ -319,6 +394,29 @@ PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int
       if (!(tt > 1e-28)) break;
     }
     const double inv = 1.0 / std::sqrt(tt);
+    if (rec && !fell_back) {
+      const int mm = m;
+      double* vm = V + (int64_t)mm * n;
+      double* wm = W + (int64_t)mm * n;
+      c->prepare(prec);  // task lists exist before the recording
+      void* g2 = dav_graph(c, prec, mm, 1, [&] {
+        ex->axpby_dev(vm, 1.0, cf + CF_INV, t, 0.0, nullptr, t, n);
+        ex->copy_d2d(c->C->ptr(c->b_in), vm, (size_t)n * 8);
+        c->enqueue_hpsi(prec);
+        ex->copy_d2d(wm, c->C->ptr(c->b_out), (size_t)n * 8);
+        ex->multidot_dev(W, n, mm + 1, vm, n, cf + CF_ROW);
+        ex->multidot_dev(V, n, mm + 1, wm, n, cf + CF_COL);
+      });
+      ex->upload(cf + CF_INV, &inv, 8);
+      ex->replay(g2);
+      std::vector<double> rc(CF_SIZE - CF_ROW);
+      ex->download(rc.data(), cf + CF_ROW, rc.size() * 8);
+      for (int j = 0; j <= m; ++j) G[(size_t)m * mmax + j] = rc[j];
+      for (int j = 0; j <= m; ++j) G[(size_t)j * mmax + m] = rc[CF_COL - CF_ROW + j];
+      res.matvecs++;
+      ++m;
+      continue;
+    }
     ex->axpby(V + (int64_t)m * n, inv, t, 0.0, t, n);
     matvec(c, V + (int64_t)m * n, W + (int64_t)m * n, prec, n);
     res.matvecs++;
@@ -335,10 +433,11 @@ PhaseResult davidson_phase(dmrg_ctx* c, Workspace& ws, int prec, double tol, int
 // Davidson buffers owned by the context (freed with the H*psi plan).
 Workspace workspace(dmrg_ctx* c, int64_t n, int mmax) {
   if (c->work_bufs.empty() || c->work_n != n || c->work_mmax != mmax) {
+    c->drop_dav_graphs();
     for (int b : c->work_bufs) c->C->free_buf(b);
     c->work_bufs = {c->C->new_buf((int64_t)(mmax + kKeep) * n), c->C->new_buf((int64_t)(mmax + kKeep) * n), c->C->new_buf(n),
                     c->C->new_buf(n), c->C->new_buf(n), c->C->new_buf(n), c->C->new_buf(n), c->C->new_buf(n),
-                    c->C->new_buf(n)};
+                    c->C->new_buf(n), c->C->new_buf(CF_SIZE)};
     c->work_n = n;
     c->work_mmax = mmax;
   }
@@ -354,6 +453,7 @@ Workspace workspace(dmrg_ctx* c, int64_t n, int mmax) {
   ws.bp = c->work_bufs[6];
   ws.bq = c->work_bufs[7];
   ws.bs = c->work_bufs[8];
+  ws.bc = c->work_bufs[9];
   return ws;
 }
 }  // namespace

@@ -107,6 +107,33 @@ class Executor {
   virtual void axpby(double* z, double a, const double* x, double b, const double* y, int64_t n) = 0;
   // t_i = r_i / (theta - d_i), with |theta - d_i| floored at eps
   virtual void precond(double* t, const double* r, const double* d, double theta, double eps, int64_t n) = 0;
+  // ---- the same primitives with scalars read from device memory, so that a
+  // Davidson iteration can be recorded as a graph and replayed with new
+  // scalars.  They launch the kernels of the host-scalar forms above (same
+  // arithmetic, same summation order, so the same results bit for bit).
+  // out_dev[i] = <V_i, w>, i < m (m <= 64)
+  virtual void multidot_dev(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out_dev) {
+    (void)V; (void)ldv; (void)m; (void)w; (void)n; (void)out_dev;
+    throw std::runtime_error("executor: no device-scalar vector primitives");
+  }
+  // y = beta*y + sum_i (sgn * c_dev[i]) * V_i   (m <= 64)
+  virtual void combine_dev(double* y, const double* V, int64_t ldv, int m, const double* c_dev, double sgn, int64_t n,
+                           double beta) {
+    (void)y; (void)V; (void)ldv; (void)m; (void)c_dev; (void)sgn; (void)n; (void)beta;
+    throw std::runtime_error("executor: no device-scalar vector primitives");
+  }
+  // z = a'*x + b'*y with a' = a * a_dev[0] (a if a_dev is null), b' likewise
+  virtual void axpby_dev(double* z, double a, const double* a_dev, const double* x, double b, const double* b_dev,
+                         const double* y, int64_t n) {
+    (void)z; (void)a; (void)a_dev; (void)x; (void)b; (void)b_dev; (void)y; (void)n;
+    throw std::runtime_error("executor: no device-scalar vector primitives");
+  }
+  // precond with theta = theta_dev[0]
+  virtual void precond_dev(double* t, const double* r, const double* d, const double* theta_dev, double eps,
+                           int64_t n) {
+    (void)t; (void)r; (void)d; (void)theta_dev; (void)eps; (void)n;
+    throw std::runtime_error("executor: no device-scalar vector primitives");
+  }
   // Batched symmetric eigensolver (FP64): matrix i is sizes[i] x sizes[i],
   // row-major at A + offs[i]; on return its diagonal holds the eigenvalues
   // (unordered) and V + offs[i] the eigenvectors as columns.  Two-sided Jacobi

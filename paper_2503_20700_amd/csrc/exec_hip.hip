@@ -1762,21 +1762,32 @@ struct Coef64 {
   double c[64];
 };
 
-__global__ void combine_kernel(double* __restrict__ y, const double* __restrict__ V, long long ldv, int m, Coef64 c,
-                               long long n, double beta) {
+// The scalar arguments come from the kernel arguments, or (a non-null device
+// pointer: launches recorded into a graph) from device memory.
+__global__ __launch_bounds__(256) void combine_kernel(double* __restrict__ y, const double* __restrict__ V,
+                                                      long long ldv, int m, Coef64 c, const double* c_dev, double sgn,
+                                                      long long n, double beta) {
+  __shared__ double cs[64];
+  if ((int)threadIdx.x < m) cs[threadIdx.x] = c_dev ? sgn * c_dev[threadIdx.x] : c.c[threadIdx.x];
+  __syncthreads();
   for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n; j += (long long)gridDim.x * blockDim.x) {
     double s = (beta == 0.0) ? 0.0 : beta * y[j];
-    for (int i = 0; i < m; ++i) s += c.c[i] * V[i * ldv + j];
+    for (int i = 0; i < m; ++i) s += cs[i] * V[i * ldv + j];
     y[j] = s;
   }
 }
 
-__global__ void axpby_kernel(double* z, double a, const double* x, double b, const double* y, long long n) {
+__global__ void axpby_kernel(double* z, double a, const double* a_dev, const double* x, double b, const double* b_dev,
+                             const double* y, long long n) {
+  if (a_dev) a *= a_dev[0];
+  if (b_dev) b *= b_dev[0];
   for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n; j += (long long)gridDim.x * blockDim.x)
     z[j] = a * x[j] + b * y[j];
 }
 
-__global__ void precond_kernel(double* t, const double* r, const double* d, double theta, double eps, long long n) {
+__global__ void precond_kernel(double* t, const double* r, const double* d, double theta, const double* theta_dev,
+                               double eps, long long n) {
+  if (theta_dev) theta = theta_dev[0];
   for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < n; j += (long long)gridDim.x * blockDim.x) {
     double den = theta - d[j];
     if (fabs(den) < eps) den = den < 0 ? -eps : eps;
@@ -2492,6 +2503,7 @@ class HipExec : public Executor {
   }
   bool graphs() const override { return true; }
   void capture_begin() override {
+    dot_buffers();  // allocated outside the recording
     HIP_OK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
     capturing_ = true;
   }
@@ -2985,34 +2997,61 @@ class HipExec : public Executor {
 #undef C_
     throw std::runtime_error("executor: unsupported conversion");
   }
-  void multidot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out_host) override {
-    if (m <= 0) return;
-    if (m > 64) throw std::runtime_error("multidot: m > 64");
+  void dot_buffers() {
     if (!dot_part_) {
       dot_part_ = (double*)alloc(sizeof(double) * kDotBlocks * 64);
       dot_out_ = (double*)alloc(sizeof(double) * 64);
     }
+  }
+  void multidot_dev(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out_dev) override {
+    if (m <= 0) return;
+    if (m > 64) throw std::runtime_error("multidot: m > 64");
+    if (!dot_part_ && capturing_) throw std::runtime_error("multidot: first use inside a graph recording");
+    dot_buffers();
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (n + 255) / 256));
     hipLaunchKernelGGL(multidot_partial, dim3(nb), dim3(256), 0, stream_, V, (long long)ldv, m, w, (long long)n,
                        dot_part_);
-    hipLaunchKernelGGL(multidot_final, dim3(1), dim3(256), 0, stream_, dot_part_, nb, m, dot_out_);
+    hipLaunchKernelGGL(multidot_final, dim3(1), dim3(256), 0, stream_, dot_part_, nb, m, out_dev);
     HIP_OK(hipGetLastError());
+  }
+  void multidot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out_host) override {
+    if (m <= 0) return;
+    dot_buffers();
+    multidot_dev(V, ldv, m, w, n, dot_out_);
     download(out_host, dot_out_, sizeof(double) * m);
   }
   void combine(double* y, const double* V, int64_t ldv, int m, const double* c_host, int64_t n, double beta) override {
     if (m > 64) throw std::runtime_error("combine: m > 64");
     Coef64 c{};
     for (int i = 0; i < m; ++i) c.c[i] = c_host[i];
-    hipLaunchKernelGGL(combine_kernel, dim3(grid1(n)), dim3(256), 0, stream_, y, V, (long long)ldv, m, c, (long long)n,
-                       beta);
+    hipLaunchKernelGGL(combine_kernel, dim3(grid1(n)), dim3(256), 0, stream_, y, V, (long long)ldv, m, c,
+                       (const double*)nullptr, 1.0, (long long)n, beta);
+    HIP_OK(hipGetLastError());
+  }
+  void combine_dev(double* y, const double* V, int64_t ldv, int m, const double* c_dev, double sgn, int64_t n,
+                   double beta) override {
+    if (m > 64) throw std::runtime_error("combine: m > 64");
+    hipLaunchKernelGGL(combine_kernel, dim3(grid1(n)), dim3(256), 0, stream_, y, V, (long long)ldv, m, Coef64{}, c_dev,
+                       sgn, (long long)n, beta);
     HIP_OK(hipGetLastError());
   }
   void axpby(double* z, double a, const double* x, double b, const double* y, int64_t n) override {
-    hipLaunchKernelGGL(axpby_kernel, dim3(grid1(n)), dim3(256), 0, stream_, z, a, x, b, y, (long long)n);
+    axpby_dev(z, a, nullptr, x, b, nullptr, y, n);
+  }
+  void axpby_dev(double* z, double a, const double* a_dev, const double* x, double b, const double* b_dev,
+                 const double* y, int64_t n) override {
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid1(n)), dim3(256), 0, stream_, z, a, a_dev, x, b, b_dev, y, (long long)n);
     HIP_OK(hipGetLastError());
   }
   void precond(double* t, const double* r, const double* d, double theta, double eps, int64_t n) override {
-    hipLaunchKernelGGL(precond_kernel, dim3(grid1(n)), dim3(256), 0, stream_, t, r, d, theta, eps, (long long)n);
+    hipLaunchKernelGGL(precond_kernel, dim3(grid1(n)), dim3(256), 0, stream_, t, r, d, theta, (const double*)nullptr,
+                       eps, (long long)n);
+    HIP_OK(hipGetLastError());
+  }
+  void precond_dev(double* t, const double* r, const double* d, const double* theta_dev, double eps,
+                   int64_t n) override {
+    hipLaunchKernelGGL(precond_kernel, dim3(grid1(n)), dim3(256), 0, stream_, t, r, d, 0.0, theta_dev, eps,
+                       (long long)n);
     HIP_OK(hipGetLastError());
   }
   int sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes, int max_sweeps,

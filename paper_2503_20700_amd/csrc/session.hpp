@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
+#include <map>
 #include <stdexcept>
 #include <memory>
 #include <string>
@@ -64,6 +65,17 @@ struct dmrg_ctx {
   std::vector<int> work_bufs;
   int64_t work_n = 0;
   int work_mmax = 0;
+  // Davidson iteration sequences recorded as graphs (opts.davidson_graph),
+  // keyed by (precision, basis size, part); they hold the addresses of the
+  // workspace and of the H*psi buffers, and are valid while both stay and
+  // the executor's scratch generation is dav_gen.
+  std::map<int, void*> dav_graphs;
+  long long dav_gen = -1;
+  void drop_dav_graphs() {
+    for (auto& g : dav_graphs) ex->drop_graph(g.second);
+    dav_graphs.clear();
+    dav_gen = -1;
+  }
 
   ~dmrg_ctx() {
     reset_plan();
@@ -79,6 +91,7 @@ struct dmrg_ctx {
   }
 
   void reset_plan() {
+    drop_dav_graphs();
     for (auto& p : prep) {
       ex->drop_graph(p.graph);
       p.graph = nullptr;

@@ -137,6 +137,11 @@ def main(argv):
             if len(argv) >= 5:
                 res["algorithmic_flops"] = float(argv[4])
                 res["executed_over_algorithmic"] = res["mfma_flops_executed"] / res["algorithmic_flops"]
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in c and c.get("GRBM_GUI_ACTIVE"):
+            # GRBM_GUI_ACTIVE is summed over the 8 XCDs; 256 CUs x 4 SIMDs
+            res["mfma_busy_fraction"] = c["SQ_VALU_MFMA_BUSY_CYCLES"] / (c["GRBM_GUI_ACTIVE"] / 8.0 * 1024.0)
+            res["note"] = ("GRBM_GUI_ACTIVE is summed over the 8 XCDs (per-XCD active cycles = sum / 8); MFMA busy = "
+                           "SQ_VALU_MFMA_BUSY_CYCLES / (per-XCD active cycles x 1024 SIMDs)")
         with open(argv[3], "w") as f:
             json.dump(res, f, indent=1)
         print(json.dumps(res, indent=1))

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 #include <vector>
 #include <algorithm>
@@ -58,19 +59,42 @@ inline void st(void* p, int dt, int64_t i, double v) {
 }
 struct Prep { std::vector<RawJob> jobs; std::vector<RawTerm> terms; int da, db, dc; };
 
+// Graph recording: between capture_begin and capture_end the queued work
+// (kernels, device copies) is kept as closures that replay() runs; calls that
+// a HIP stream recording refuses (allocation, host transfers, waits,
+// preparation) throw, so the driver's recorded sequences are checked for them.
+typedef std::vector<std::function<void()>> Graph;
+
 class CpuExec : public Executor {
+  Graph* rec_ = nullptr;
+  void queue(std::function<void()> f) {
+    if (rec_) rec_->push_back(std::move(f));
+    else f();
+  }
+  void no_rec(const char* what) const {
+    if (rec_) throw std::runtime_error(std::string("executor: ") + what + " inside a graph recording");
+  }
+
  public:
-  void* alloc(size_t b) override { void* p = std::malloc(b ? b : 1); if (!p) throw std::bad_alloc(); return p; }
-  void release(void* p) override { std::free(p); }
-  void upload(void* d, const void* s, size_t b) override { if (b) std::memcpy(d, s, b); }
-  void download(void* d, const void* s, size_t b) override { if (b) std::memcpy(d, s, b); }
-  void zero(void* p, size_t b) override { if (b) std::memset(p, 0, b); }
-  void copy_d2d(void* d, const void* s, size_t b) override { if (b) std::memmove(d, s, b); }
+  void* alloc(size_t b) override { no_rec("alloc"); void* p = std::malloc(b ? b : 1); if (!p) throw std::bad_alloc(); return p; }
+  void release(void* p) override { no_rec("release"); std::free(p); }
+  void upload(void* d, const void* s, size_t b) override { no_rec("upload"); if (b) std::memcpy(d, s, b); }
+  void download(void* d, const void* s, size_t b) override { no_rec("download"); if (b) std::memcpy(d, s, b); }
+  void zero(void* p, size_t b) override { queue([=] { if (b) std::memset(p, 0, b); }); }
+  void copy_d2d(void* d, const void* s, size_t b) override { queue([=] { if (b) std::memmove(d, s, b); }); }
   void* prepare(const std::vector<RawJob>& jobs, const std::vector<RawTerm>& terms, int da, int db, int dc) override {
+    no_rec("prepare");
     auto* P = new Prep{jobs, terms, da, db, dc};
     return P;
   }
-  void run(void* h) override {
+  bool graphs() const override { return true; }
+  void capture_begin() override { no_rec("capture_begin"); rec_ = new Graph(); }
+  void* capture_end() override { Graph* g = rec_; rec_ = nullptr; return g; }
+  void capture_abort() override { delete rec_; rec_ = nullptr; }
+  void replay(void* g) override { no_rec("replay"); for (auto& f : *(Graph*)g) f(); }
+  void drop_graph(void* g) override { delete (Graph*)g; }
+  void run(void* h) override { queue([=] { run_now(h); }); }
+  void run_now(void* h) {
     auto* P = (Prep*)h;
     const bool low = P->da != DT_F64;
     for (size_t jj = 0; jj < P->jobs.size(); ++jj) {
@@ -147,18 +171,46 @@ class CpuExec : public Executor {
   }
   void place_fixed(void*, void*, void*) override {}
   void drop_fixed(void* h) override { delete (Prep*)h; }
-  void sync() override {}
-  void multidot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out) override {
+  void sync() override { no_rec("sync"); }
+  static void dots(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out) {
     for (int i = 0; i < m; ++i) { double s = 0; for (int64_t j = 0; j < n; ++j) s += V[i * ldv + j] * w[j]; out[i] = s; }
   }
-  void combine(double* y, const double* V, int64_t ldv, int m, const double* c, int64_t n, double beta) override {
-    for (int64_t j = 0; j < n; ++j) { double s = beta == 0.0 ? 0.0 : beta * y[j]; for (int i = 0; i < m; ++i) s += c[i] * V[i * ldv + j]; y[j] = s; }
+  static void comb(double* y, const double* V, int64_t ldv, int m, const double* c, double sgn, int64_t n, double beta) {
+    for (int64_t j = 0; j < n; ++j) { double s = beta == 0.0 ? 0.0 : beta * y[j]; for (int i = 0; i < m; ++i) s += sgn * c[i] * V[i * ldv + j]; y[j] = s; }
   }
-  void axpby(double* z, double a, const double* x, double b, const double* y, int64_t n) override {
+  static void axpb(double* z, double a, const double* x, double b, const double* y, int64_t n) {
     for (int64_t j = 0; j < n; ++j) z[j] = a * x[j] + b * y[j];
   }
-  void precond(double* t, const double* r, const double* d, double theta, double eps, int64_t n) override {
+  static void prec(double* t, const double* r, const double* d, double theta, double eps, int64_t n) {
     for (int64_t j = 0; j < n; ++j) { double den = theta - d[j]; if (std::fabs(den) < eps) den = den < 0 ? -eps : eps; t[j] = r[j] / den; }
+  }
+  void multidot(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out) override {
+    no_rec("multidot to the host");
+    dots(V, ldv, m, w, n, out);
+  }
+  void combine(double* y, const double* V, int64_t ldv, int m, const double* c, int64_t n, double beta) override {
+    std::vector<double> cv(c, c + m);  // host coefficients are taken at the call
+    queue([=] { comb(y, V, ldv, m, cv.data(), 1.0, n, beta); });
+  }
+  void axpby(double* z, double a, const double* x, double b, const double* y, int64_t n) override {
+    queue([=] { axpb(z, a, x, b, y, n); });
+  }
+  void precond(double* t, const double* r, const double* d, double theta, double eps, int64_t n) override {
+    queue([=] { prec(t, r, d, theta, eps, n); });
+  }
+  void multidot_dev(const double* V, int64_t ldv, int m, const double* w, int64_t n, double* out) override {
+    queue([=] { dots(V, ldv, m, w, n, out); });
+  }
+  void combine_dev(double* y, const double* V, int64_t ldv, int m, const double* c, double sgn, int64_t n,
+                   double beta) override {
+    queue([=] { comb(y, V, ldv, m, c, sgn, n, beta); });
+  }
+  void axpby_dev(double* z, double a, const double* a_dev, const double* x, double b, const double* b_dev,
+                 const double* y, int64_t n) override {
+    queue([=] { axpb(z, a_dev ? a * a_dev[0] : a, x, b_dev ? b * b_dev[0] : b, y, n); });
+  }
+  void precond_dev(double* t, const double* r, const double* d, const double* theta, double eps, int64_t n) override {
+    queue([=] { prec(t, r, d, theta[0], eps, n); });
   }
   int sym_eig(double* A, double* V, const std::vector<int64_t>& offs, const std::vector<int>& sizes, int max_sweeps,
                double tol, double* worst) override {
@@ -185,12 +237,14 @@ class CpuExec : public Executor {
     return 0;
   }
   void pack(void* dst, int dd, const double* src, const int* idx, size_t n) override {
-    for (size_t i = 0; i < n; ++i) st(dst, dd, i, idx[i] >= 0 ? src[idx[i]] : 0.0);
+    queue([=] { for (size_t i = 0; i < n; ++i) st(dst, dd, i, idx[i] >= 0 ? src[idx[i]] : 0.0); });
   }
   void gather(double* dst, const void* src, int ds, const int* idx, size_t n, double a, const double* x,
               const double* mul) override {
-    const double m = mul ? mul[0] : 1.0;
-    for (size_t i = 0; i < n; ++i) dst[i] = m * ld(src, ds, idx[i]) + (x ? a * x[i] : 0.0);
+    queue([=] {
+      const double m = mul ? mul[0] : 1.0;
+      for (size_t i = 0; i < n; ++i) dst[i] = m * ld(src, ds, idx[i]) + (x ? a * x[i] : 0.0);
+    });
   }
   static void pow2(double m, double* out) {
     int e = 0;
@@ -208,9 +262,11 @@ class CpuExec : public Executor {
   }
   void pack_fp8(void* dst, const double* src, const int* idx, size_t n, double* d_scale, const double* src_all,
                 size_t n_all) override {
-    double m = 0; for (size_t i = 0; i < n_all; ++i) m = std::max(m, std::fabs(src_all[i]));
-    pow2(m, d_scale);
-    for (size_t i = 0; i < n; ++i) ((unsigned char*)dst)[i] = idx[i] >= 0 ? e4m3_enc(src[idx[i]] * d_scale[1]) : 0;
+    queue([=] {
+      double m = 0; for (size_t i = 0; i < n_all; ++i) m = std::max(m, std::fabs(src_all[i]));
+      pow2(m, d_scale);
+      for (size_t i = 0; i < n; ++i) ((unsigned char*)dst)[i] = idx[i] >= 0 ? e4m3_enc(src[idx[i]] * d_scale[1]) : 0;
+    });
   }
   void shifted_copy_at(void* dst, int dd, const double* src, const int* idx, size_t n, double a) override {
     for (size_t i = 0; i < n; ++i) st(dst, dd, idx[i], src[idx[i]] + a);

@@ -103,7 +103,7 @@ def test_create_rejects_integrals_without_their_symmetries_and_a_negative_budget
     with pytest.raises(DMRGError) as e:
         DMRG(h, g, 4, 0, hbm_budget_bytes=-1)
     assert e.value.code == -1
-    for bad in (dict(keep_blocks=-1), dict(davidson_mid_fp32=2)):
+    for bad in (dict(keep_blocks=-1), dict(davidson_mid_fp32=2), dict(davidson_graph=2)):
         with pytest.raises(DMRGError) as e:
             DMRG(h, g, 4, 0, **bad)
         assert e.value.code == -1, bad

@@ -132,3 +132,35 @@ def test_davidson_fp32_middle_phase(prec, case):
         assert abs(r["energy"] - e_ref) <= 1e-6
         res[mid] = r
     assert res[True]["n_fp64"] <= res[False]["n_fp64"]
+
+
+@pytest.mark.parametrize("prec,extra", [(0, {}), (2, {"davidson_mid_fp32": True}), (3, {}), (2, {"hpsi_graph": True})],
+                         ids=["fp64", "bf16+fp32+fp64", "fp8+fp64", "bf16+hpsi_graph"])
+@pytest.mark.parametrize("case", [(8, 8, 0, 64, 3, 0), (7, 7, 1, 16, 2, 3)], ids=["cas88_s0", "cas77_s1/2"])
+def test_davidson_recorded_iterations_equal_eager(prec, extra, case):
+    """davidson_graph: the device work of each Davidson iteration replayed
+    from recorded HIP graphs gives the eager iteration's eigenpair bit for bit
+    and the same matvec counts -- with restarts between recorded iterations
+    (subspace 8), and on a second solve from a new start, which replays the
+    graphs recorded by the first -- and the dense eigenvalue to 1e-6 Eh."""
+    from paper_2503_20700_amd.binding import DMRG
+    n, ne, ts, d, k, seed = case
+    print(f"[davidson recorded] prec={prec} {extra} case={case}", flush=True)
+    h, g, _ = small_cas(n, seed)
+    mps = random_mps(n, ne, ts, d, k=k, seed=seed + 100)
+    psi, lay = random_psi(mps, seed=seed + 200)
+    psi2 = psi + 0.3 * np.random.default_rng(seed).normal(size=psi.size)
+    e_ref = np.linalg.eigvalsh(heff.HeffDefinition(h, g, mps, lay).dense())[0]
+    out = {}
+    for rec in (False, True):
+        dm = DMRG(h, g, ne, ts, hpsi_prec=prec, davidson_max_iter=300, davidson_max_subspace=8, davidson_graph=rec,
+                  **extra)
+        bs, cnt = mps.bond_table()
+        dm.set_mps(k, bs, cnt, mps.site_blocks_flat())
+        out[rec] = [dm.davidson(psi), dm.davidson(psi2)]
+        dm.close()
+    for a, b in zip(out[False], out[True]):
+        assert a["converged"] and b["converged"]
+        assert a["energy"] == b["energy"] and np.array_equal(a["psi"], b["psi"])
+        assert (a["n_lo"], a["n_fp64"]) == (b["n_lo"], b["n_fp64"])
+        assert abs(b["energy"] - e_ref) <= 1e-6

@@ -6,9 +6,9 @@ compiled with -fsanitize=address,undefined into a separate library together
 with tests/asan/host_executor.cpp, a plain-loop stand-in for the HIP
 executor; a child Python process then drives that library through the
 binding over a small workload -- H*psi in every precision, Davidson with and
-without the FP32 middle phase, truncation both ways with carried start
-vectors, checkpoint and resume, a batch of two instances, the orbital step
-and the argument checks.  Any sanitizer report fails the test.  The product
+without the FP32 middle phase, Davidson iterations recorded as graphs against
+eager ones, truncation both ways with carried start vectors, checkpoint and
+resume, a batch of two instances, the orbital step and the argument checks.  Any sanitizer report fails the test.  The product
 library is not involved: this checks the host-side index arithmetic, which
 the GPU tests exercise only through results."""
 import os
@@ -62,6 +62,21 @@ for x in (a, b):
 bt = HpsiBatch([a, b], 0)
 bt.davidson([psi, psi])
 bt.close()
+# Davidson iterations recorded as graphs (replayed closures on this
+# executor) against the eager iteration: the same eigenpair bit for bit and
+# the same matvec counts, with restarts (subspace 8) between recorded steps
+for prec, extra in ((0, {}), (2, dict(davidson_mid_fp32=True)), (2, dict(davidson_jd_inner=4))):
+    res = []
+    for rec in (False, True):
+        x = DMRG(h, g, ne, ts, hpsi_prec=prec, davidson_max_iter=80, davidson_max_subspace=8,
+                 davidson_graph=rec, hpsi_graph=rec, **extra)
+        x.set_mps(k, bs, cnt, mps.site_blocks_flat())
+        res.append(x.davidson(psi))
+        x.close()
+    e, f = res
+    assert e["energy"] == f["energy"] and np.array_equal(e["psi"], f["psi"]), (prec, extra)
+    assert (e["n_lo"], e["n_fp64"]) == (f["n_lo"], f["n_fp64"]), (prec, extra, e["n_lo"], f["n_lo"])
+    print("recorded iterations", prec, extra, e["n_lo"], e["n_fp64"], flush=True)
 for bad in (lambda: DMRG(h, g, ne, ts, keep_blocks=-1), lambda: dm.hpsi(psi[:-1]), lambda: dm.truncate(psi, 0, 0.0, 1)):
     try:
         bad()
