@@ -1,5 +1,6 @@
 """Host-side logic with no GPU: the 48-instance workload recipe and the
-arithmetic that turns rocprofv3 counter files into HBM bytes."""
+arithmetic that turns rocprofv3 counter files into HBM bytes and MFMA
+figures."""
 import csv
 import json
 import os
@@ -72,3 +73,45 @@ def test_bench_reports_traffic_only_for_the_kernel_source_it_was_taken_on():
     else:
         assert total is None and detail is None
     assert bench.measured_traffic("cas32_d1024") == (None, None)
+
+
+def test_mfma_counters_give_executed_flops_and_busy_fraction(tmp_path):
+    # several counters per dispatch; the last two BF16 GEMM dispatches form
+    # the H*psi.  One BF16 MFMA MOP is 512 flops; GRBM_GUI_ACTIVE is summed
+    # over the 8 XCDs and the busy cycles over the 1024 SIMDs.
+    import rocprof_summary as rs
+    rows = []
+    for di, name, mops, busy, grbm in ((1, "void gemm_bf16_pipe<2, 64, 64, 3>(...)", 5.0, 7.0, 8.0),
+                                       (2, "void gemm_bf16_pipe<2, 64, 64, 3>(...)", 100.0, 1024.0, 64.0),
+                                       (3, "void gemm_bf16_padded<1, 64, 64, false, false>(...)", 300.0, 3072.0, 64.0),
+                                       (4, "void reduce_kernel<1>(...)", 1e6, 1e6, 1e6)):
+        for cname, v in (("SQ_INSTS_VALU_MFMA_MOPS_BF16", mops), ("SQ_VALU_MFMA_BUSY_CYCLES", busy),
+                         ("GRBM_GUI_ACTIVE", grbm)):
+            rows.append({"Dispatch_Id": di, "Kernel_Name": name, "Counter_Name": cname, "Counter_Value": v})
+    os.makedirs(tmp_path / "m", exist_ok=True)
+    with open(tmp_path / "m" / "run_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+    out = tmp_path / "m.json"
+    assert rs.main(["counters", str(tmp_path / "m"), "2", str(out), "102400"]) == 0
+    m = json.loads(out.read_text())
+    assert m["launches"] == 2 and m["counters"]["SQ_INSTS_VALU_MFMA_MOPS_BF16"] == 400.0
+    assert m["mfma_flops_executed"] == 400.0 * 512 and abs(m["executed_over_algorithmic"] - 2.0) < 1e-12
+    # 4096 busy SIMD cycles over 128 / 8 = 16 active cycles x 1024 SIMDs
+    assert abs(m["mfma_busy_fraction"] - 4096.0 / (16.0 * 1024.0)) < 1e-12
+    assert m["source_sha256"] == rs.source_sha256()
+
+
+def test_bench_reports_mfma_counters_only_for_the_kernel_source_they_were_taken_on():
+    import bench
+    from rocprof_summary import source_sha256
+    with open(bench.MFMA_FILE) as f:
+        m = json.load(f)
+    got = bench.measured_mfma("cas82_d4096")
+    if m["source_sha256"] == source_sha256():
+        assert got["busy_fraction"] == m["mfma_busy_fraction"] and got["launches"] == m["launches"]
+    else:
+        assert got is None
+    assert bench.measured_mfma("cas32_d1024") is None
