@@ -9,7 +9,7 @@ reports the mixed-precision throughput, the FP64 throughput and their
 agreement.  Operator blocks are built once before timing (set-up, reported).
 
 Prints one JSON line (see the fields below).  --gpus > 1 is not supported:
-this build runs on one GPU.
+the library runs one context per GPU and has no multi-GPU path.
 """
 import argparse
 import json
@@ -277,7 +277,8 @@ def main():
                     help="first run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library has no multi-GPU path (H*psi runs on one GPU); --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
     if args.config == "batch48":
         batch_main(args)

@@ -62,7 +62,7 @@ struct Prep { std::vector<RawJob> jobs; std::vector<RawTerm> terms; int da, db, 
 // Graph recording: between capture_begin and capture_end the queued work
 // (kernels, device copies) is kept as closures that replay() runs; calls that
 // a HIP stream recording refuses (allocation, host transfers, waits,
-// preparation) throw, so the driver's recorded sequences are checked for them.
+// preparation) throw, so the Davidson iteration's recorded sequences are checked for them.
 typedef std::vector<std::function<void()>> Graph;
 
 class CpuExec : public Executor {
