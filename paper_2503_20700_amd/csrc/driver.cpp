@@ -119,6 +119,8 @@ bool dav_graph_on(dmrg_ctx* c, int jd_steps) {
   return c->opts.davidson_graph && jd_steps == 0 && !c->mv_hook && c->ex->graphs() && !c->ex->timing_on();
 }
 
+// The recorded sequence `part` for precision prec and basis size m: recorded
+// from `body` on first use, and again after the executor's scratch moved.
 void* dav_graph(dmrg_ctx* c, int prec, int m, int part, const std::function<void()>& body) {
   Executor* ex = c->ex.get();
   if (c->dav_gen != ex->scratch_generation()) {
