@@ -65,13 +65,25 @@ bt.close()
 # Davidson iterations recorded as graphs (replayed closures on this
 # executor) against the eager iteration: the same eigenpair bit for bit and
 # the same matvec counts, with restarts (subspace 8) between recorded steps
-for prec, extra in ((0, {}), (2, dict(davidson_mid_fp32=True)), (2, dict(davidson_jd_inner=4))):
+mps_h = random_mps(7, 7, 1, 12, k=2, seed=9)  # a doublet
+psi_h, _ = random_psi(mps_h, seed=10)
+h7, g7, _ = small_cas(7, 3)
+cases = [(0, {}, None), (2, dict(davidson_mid_fp32=True), None), (2, dict(davidson_jd_inner=4), None),
+         (3, {}, None), (2, {}, "doublet")]
+for prec, extra, which in cases:
     res = []
     for rec in (False, True):
-        x = DMRG(h, g, ne, ts, hpsi_prec=prec, davidson_max_iter=80, davidson_max_subspace=8,
-                 davidson_graph=rec, hpsi_graph=rec, **extra)
-        x.set_mps(k, bs, cnt, mps.site_blocks_flat())
-        res.append(x.davidson(psi))
+        if which is None:
+            x = DMRG(h, g, ne, ts, hpsi_prec=prec, davidson_max_iter=80, davidson_max_subspace=8,
+                     davidson_graph=rec, hpsi_graph=rec, **extra)
+            x.set_mps(k, bs, cnt, mps.site_blocks_flat())
+            res.append(x.davidson(psi))
+        else:
+            x = DMRG(h7, g7, 7, 1, hpsi_prec=prec, davidson_max_iter=80, davidson_max_subspace=8,
+                     davidson_graph=rec, **extra)
+            b7, c7 = mps_h.bond_table()
+            x.set_mps(2, b7, c7, mps_h.site_blocks_flat())
+            res.append(x.davidson(psi_h))
         x.close()
     e, f = res
     assert e["energy"] == f["energy"] and np.array_equal(e["psi"], f["psi"]), (prec, extra)
