@@ -115,3 +115,20 @@ def test_bench_reports_mfma_counters_only_for_the_kernel_source_they_were_taken_
     else:
         assert got is None
     assert bench.measured_mfma("cas32_d1024") is None
+
+
+def test_e4m3_reference_quantizer_matches_the_format():
+    """The numpy E4M3 quantizer the FP8 GPU tests compare against: 127 finite
+    non-negative values, largest 448, smallest subnormal 2^-9, and round to
+    nearest with ties to the even code (facts of the OCP 8-bit float format)."""
+    from tests.test_gpu_kernel import _e4m3_values, _quantize_e4m3
+    v = _e4m3_values()
+    assert len(v) == 127 and v[0] == 0.0 and v[1] == 2.0 ** -9 and v[-1] == 448.0
+    assert v[8] == 2.0 ** -6  # first normal: exponent field 1, mantissa 0
+    x = np.array([1.0625, 1.1875, -1.0625, 2.0 ** -10, 3 * 2.0 ** -10, 500.0, -1e9, 0.3])
+    # 1.0625 lies halfway between 1 (code 0x38, even) and 1.125 (0x39): 1;
+    # 1.1875 between 1.125 (0x39) and 1.25 (0x3a, even): 1.25; half the
+    # smallest subnormal ties to 0 (even); 1.5 * 2^-9 ties to 2^-8 (code 2);
+    # beyond 448 saturates; 0.3 rounds to 0.3125 (nearest: 0.28125 / 0.3125)
+    want = np.array([1.0, 1.25, -1.0, 0.0, 2.0 ** -8, 448.0, -448.0, 0.3125])
+    assert np.array_equal(_quantize_e4m3(x), want)
